@@ -1,0 +1,314 @@
+/*
+ * hiccl.h — C ABI of a hierarchical collective executor for one MI355X (gfx950).
+ *
+ * Method: HiCCL (arXiv 2408.05962). A collective is composed from multicast,
+ * reduction and fence primitives (Sec. 3, Listing 1), factorized onto a
+ * stated multilevel hierarchy as point-to-point transfers within each level
+ * (Sec. 4.2), striped (Sec. 4.3) and pipelined (Sec. 4.5), and executed
+ * without a global barrier (Sec. 5.2).
+ *
+ * Virtual ranks. The P ranks of the hierarchy are disjoint buffers in the
+ * memory of ONE GPU. Where the paper's API takes each process's own send
+ * and receive pointer, this API takes an array of P per-rank buffers with
+ * any offset already applied; only the entries a primitive uses are read.
+ * A "transfer" is a copy in device memory; a reduction node is a fused
+ * multi-operand elementwise kernel.
+ *
+ * Conventions for every entry point:
+ *   - returns HICCL_SUCCESS (0) or a negative hiccl_result; no exception
+ *     crosses the ABI; hiccl_last_error() gives a thread-local message;
+ *   - a failed call leaves the communicator as it was;
+ *   - a communicator is not thread-safe; calls on one communicator must be
+ *     serialized by the caller.
+ *
+ * Ownership: user buffers stay owned by the caller and must stay valid and
+ * unmoved while a communicator that names them exists. The library copies
+ * rank arrays and leaf vectors at registration, and owns its schedule, its
+ * device task table and (unless the caller supplies one) its workspace.
+ */
+#ifndef HICCL_H
+#define HICCL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hiccl_comm_s* hiccl_comm_t;
+typedef struct hiccl_batch_s* hiccl_batch_t;
+typedef struct hiccl_server_s* hiccl_server_t;
+
+/* One virtual rank's buffer. `data` points at element 0 (device memory for
+ * hiccl_run, host memory for hiccl_validate_host). `scales` is used by the
+ * fp8 payload only: one float per block of 256 consecutive elements, the
+ * scale of the block that starts at `data`; NULL for other types. */
+typedef struct {
+  void* data;
+  float* scales;
+} hiccl_buf_t;
+
+typedef enum {
+  HICCL_INT32 = 0,
+  HICCL_FLOAT32 = 1,
+  HICCL_BFLOAT16 = 2,   /* payload bf16, sums accumulated in float32 */
+  HICCL_FP8_E4M3 = 3    /* OCP e4m3 payload + float32 scale per 256 elements */
+} hiccl_dtype;
+
+/* Reduction operators (Sec. 3.1 names sum, max, logical-or and others;
+ * sum, max and min are provided; bf16 and fp8 support sum only). */
+typedef enum { HICCL_SUM = 0, HICCL_MAX = 1, HICCL_MIN = 2 } hiccl_op;
+
+typedef enum {
+  HICCL_SUCCESS = 0,
+  HICCL_ERR_INVALID_ARG = -1,
+  HICCL_ERR_STATE = -2,        /* call not allowed in the communicator's state */
+  HICCL_ERR_RACE = -3,         /* two primitives of one step overlap (write-write or read-write) */
+  HICCL_ERR_OOM = -4,
+  HICCL_ERR_HIP = -5,          /* HIP runtime error; message in hiccl_last_error() */
+  HICCL_ERR_TIMEOUT = -6,      /* the executor's bounded dependency wait expired */
+  HICCL_ERR_UNSUPPORTED = -7,
+  HICCL_ERR_BUSY = -8          /* serving: request deferred, HBM budget or slots exhausted */
+} hiccl_result;
+
+/* Executor forms. */
+typedef enum {
+  HICCL_EXEC_PERSISTENT = 0,   /* one launch; tiles claimed in dependency order, progress in device counters */
+  HICCL_EXEC_STAGED = 1        /* one launch per dependency stage (kernel boundaries act as fences) */
+} hiccl_exec_mode;
+
+/* Claim order of the task table. */
+typedef enum {
+  HICCL_ORDER_STAGE = 0,       /* by dependency stage, then program order */
+  HICCL_ORDER_PROGRAM = 1      /* program order (primitive, branch, channel) */
+} hiccl_order;
+
+/* ---------------------------------------------------------------- lifecycle */
+
+/* Create a communicator over `nranks` virtual ranks carrying `dtype`
+ * elements. Defaults: hierarchy {nranks} (direct), stripe 1, ring 1,
+ * pipeline 1 (Listing 2 defaults). Errors: INVALID_ARG for nranks < 1 or an
+ * unknown dtype. */
+int hiccl_comm_create(int nranks, int dtype, hiccl_comm_t* out);
+
+/* Free the communicator, its schedule, its device tables and its own
+ * workspace. Blocks until a run in flight has finished. NULL is accepted. */
+int hiccl_comm_destroy(hiccl_comm_t comm);
+
+/* --------------------------------------------------------------- composition */
+
+/* Register the multicast M(root, leaves, count) of Sec. 3.1: rank `root`'s
+ * `count` elements at send[root] are replicated to recv[j] for every j in
+ * leaves[0..nleaves). `send` and `recv` are arrays of nranks entries.
+ * A leaf equal to the root receives a local copy unless send[root] and
+ * recv[root] are the same address (in place).
+ * Errors: INVALID_ARG (rank out of range, duplicate leaf, NULL buffer,
+ * fp8 count not a multiple of 256, partially overlapping in-place buffers),
+ * STATE (after hiccl_init), RACE (overlaps a primitive of the current step). */
+int hiccl_add_multicast(hiccl_comm_t comm, const hiccl_buf_t* send, const hiccl_buf_t* recv,
+                        size_t count, int root, const int* leaves, int nleaves);
+
+/* Register the reduction R(leaves, root, count, op) of Sec. 3.1: the
+ * elementwise `op` of send[i][0..count) over i in leaves is written to
+ * recv[root]. One leaf makes a point-to-point copy (the unary operation
+ * omitted). Operands are combined in a fixed, schedule-determined order,
+ * so results are reproducible bit for bit. Errors as hiccl_add_multicast,
+ * plus UNSUPPORTED for max/min on bf16 or fp8. */
+int hiccl_add_reduction(hiccl_comm_t comm, const hiccl_buf_t* send, const hiccl_buf_t* recv,
+                        size_t count, const int* leaves, int nleaves, int root, int op);
+
+/* Close the current step (Sec. 3.3). Primitives after the fence depend on
+ * those before it only where their memory ranges overlap; there is no
+ * barrier. Errors: STATE after init. */
+int hiccl_add_fence(hiccl_comm_t comm);
+
+/* ------------------------------------------------------ optimization space */
+
+/* Hierarchy factors, highest level first (Sec. 4.1 item 1, Sec. 4.2);
+ * their product must equal nranks. Consecutive ranks fill the innermost
+ * groups. Setting a parameter after init discards the plan (init again). */
+int hiccl_set_hierarchy(hiccl_comm_t comm, const int* factors, int nlevels);
+
+/* Striping factor s (Sec. 4.1 item 3, Sec. 4.3). Must divide some group
+ * size of the hierarchy, else init fails with INVALID_ARG. Default 1. */
+int hiccl_set_stripe(hiccl_comm_t comm, int s);
+
+/* Ring length n across top-level groups (Sec. 4.4). n = 1 is the tree.
+ * n > 1 must divide the first hierarchy factor. Default 1. */
+int hiccl_set_ring(hiccl_comm_t comm, int n);
+
+/* Pipeline depth m (Sec. 4.1 item 5, Sec. 4.5): every branch is split into
+ * m channels. Default 1. */
+int hiccl_set_pipeline(hiccl_comm_t comm, int m);
+
+/* Executor launch options (not a paper parameter): form (hiccl_exec_mode),
+ * tile size in bytes (work unit claimed by one workgroup; 0 = default
+ * 64 KiB, rounded to whole 16-byte vectors and whole fp8 scale blocks),
+ * grid (workgroups; 0 = fill the device), claim order (hiccl_order). */
+int hiccl_set_exec(hiccl_comm_t comm, int mode, size_t tile_bytes, int grid, int order);
+
+/* ------------------------------------------------------------------ init */
+
+/* Factorize every primitive (striping, ring, tree — in that order, Sec. 4.4
+ * last paragraph), split into channels, derive the dependency DAG from
+ * memory-range overlaps across fences, order and tile the tasks, and size
+ * the workspace. Host-only; the device tables are uploaded on the first
+ * run (memoized, Sec. 5.2). Errors: INVALID_ARG (bad parameters),
+ * STATE (already initialized). */
+int hiccl_init(hiccl_comm_t comm);
+
+/* Bytes of device workspace the plan needs (partial sums and staged stripes). */
+int hiccl_workspace_size(hiccl_comm_t comm, size_t* bytes);
+
+/* Use caller-owned device memory (>= hiccl_workspace_size bytes, 256-byte
+ * aligned) as the workspace instead of a library allocation. */
+int hiccl_set_workspace(hiccl_comm_t comm, void* dptr, size_t bytes);
+
+/* --------------------------------------------------------------- execution */
+
+/* start() of Listing 2: enqueue the whole collective on `stream` (a
+ * hipStream_t; NULL = default stream) and return. The first call uploads
+ * the task table. Re-running on the same stream is ordered; a run on a
+ * second stream while one is in flight returns STATE. Errors: STATE (not
+ * initialized), HIP, OOM. */
+int hiccl_run(hiccl_comm_t comm, void* stream);
+
+/* wait() of Listing 2: block the host until the last run's buffers may be
+ * reused. Returns TIMEOUT if the executor gave up a dependency wait. */
+int hiccl_wait(hiccl_comm_t comm);
+
+/* Bounded-wait budget of the persistent executor, in polls of a dependency
+ * counter (default 2^22, a few seconds). Expiry aborts the run cleanly:
+ * every workgroup exits and hiccl_wait returns TIMEOUT. */
+int hiccl_set_spin_limit(hiccl_comm_t comm, uint32_t polls);
+
+/* ------------------------------------------------------------- accounting */
+
+/* Logical bytes per level of ANY accounting hierarchy `acct` (product =
+ * nranks), for the initialized plan: level_bytes[0] = local copies,
+ * level_bytes[k] = transfers whose endpoints first differ at depth k
+ * (1 = highest). A reduction node counts one transfer per operand held by
+ * another rank. hbm_read / hbm_written = bytes the executor reads and
+ * writes in device memory (every task; fp8 scales included). Any output
+ * pointer may be NULL. */
+int hiccl_query_bytes(hiccl_comm_t comm, const int* acct, int nacct, uint64_t* level_bytes,
+                      uint64_t* hbm_read, uint64_t* hbm_written);
+
+#define HICCL_INFO_MAX_SRC 16
+
+/* One task of the plan, as exported for inspection. */
+typedef struct {
+  int kind;            /* 0 copy, 1 reduce */
+  int prim;            /* registration index of the primitive */
+  int step;            /* fence-delimited step of that primitive */
+  int stripe;          /* stripe index (0 if not striped) */
+  int channel;         /* pipeline channel */
+  int stage;           /* dependency depth: 0 for tasks with no predecessor */
+  int dst_rank;        /* rank that owns the written buffer */
+  int dst_workspace;   /* 1 if the destination is library workspace */
+  int nsrc;
+  int src_rank[HICCL_INFO_MAX_SRC];
+  int npred;           /* predecessors in the DAG */
+  int ring_step;       /* 0 for tree hops; ring position otherwise */
+  uint64_t count;      /* elements */
+  uint64_t offset;     /* element offset inside the primitive */
+} hiccl_task_info_t;
+
+typedef struct {
+  uint64_t ntasks, ntiles, nedges, nstages;
+  uint64_t workspace_bytes;
+  uint64_t hbm_read, hbm_written;
+  uint64_t tile_elems;
+} hiccl_plan_info_t;
+
+int hiccl_plan_info(hiccl_comm_t comm, hiccl_plan_info_t* info);
+
+/* Copy up to `cap` task descriptions, in claim order, into `out`. */
+int hiccl_plan_tasks(hiccl_comm_t comm, hiccl_task_info_t* out, size_t cap, size_t* n);
+
+/* Schedule checker (debugging aid; never used by hiccl_run): executes the
+ * plan on HOST memory — the registered buffers must be host pointers — in
+ * `norders` random dependency-respecting orders with poisoned workspace,
+ * so a missing dependency edge shows up as a wrong result. Results of the
+ * last order are left in the receive buffers. */
+int hiccl_validate_host(hiccl_comm_t comm, uint64_t seed, int norders);
+
+/* ---------------------------------------------------------------- batching */
+
+typedef enum {
+  HICCL_BATCH_PERSISTENT = 0,  /* all task tables merged into one persistent launch */
+  HICCL_BATCH_GRAPH = 1,       /* one launch per collective, captured once into a hipGraph and replayed */
+  HICCL_BATCH_SERIAL = 2       /* one launch per collective on the stream (reference form) */
+} hiccl_batch_mode;
+
+/* Group initialized communicators (any mix of dtypes and hierarchies) into
+ * one batch. The communicators must outlive the batch and must not run on
+ * their own while it exists. */
+int hiccl_batch_create(const hiccl_comm_t* comms, int n, int mode, hiccl_batch_t* out);
+int hiccl_batch_run(hiccl_batch_t batch, void* stream);
+int hiccl_batch_wait(hiccl_batch_t batch);
+/* Device completion times (ns, from the device clock, relative to the
+ * batch start) of each collective of the last run: the moment its last
+ * task retired. `ns` has n entries. */
+int hiccl_batch_times(hiccl_batch_t batch, uint64_t* ns, int n);
+int hiccl_batch_destroy(hiccl_batch_t batch);
+
+/* Autotuner: times every (stripe, pipeline, tile) candidate on `stream`
+ * (`reps` runs each after one warm-up) and re-initializes the communicator
+ * with the fastest. Candidates that are invalid for the hierarchy are
+ * skipped. Writes the choice and its median time (microseconds). */
+int hiccl_autotune(hiccl_comm_t comm, const int* stripes, int nstripes, const int* pipes, int npipes,
+                   const size_t* tiles, int ntiles, int reps, void* stream, int* best_stripe,
+                   int* best_pipe, size_t* best_tile, double* best_us);
+
+/* ----------------------------------------------------------------- serving */
+
+/* Admission and slot manager for a stream of collective requests
+ * (continuous batching). Up to `slots` admitted requests run concurrently,
+ * each on its own stream; the device memory a request keeps resident
+ * (`footprint`: its buffers and workspace) is charged against `hbm_budget`
+ * bytes from admission until it has finished. A request that arrives while
+ * others run is admitted as soon as a slot and enough budget are free. */
+int hiccl_server_create(size_t hbm_budget, int slots, hiccl_server_t* out);
+/* Reserve a slot and `footprint` bytes for a new request. Returns BUSY when
+ * no slot or not enough budget is free right now (call progress and retry),
+ * INVALID_ARG when the footprint exceeds the whole budget. */
+int hiccl_server_admit(hiccl_server_t srv, size_t footprint, uint64_t* ticket);
+/* The stream (hipStream_t) of an admitted request's slot, for the caller's
+ * own preparation work before the launch. */
+int hiccl_server_stream(hiccl_server_t srv, uint64_t ticket, void** stream);
+/* Start an admitted request: enqueue `comm` (initialized) on its slot. */
+int hiccl_server_launch(hiccl_server_t srv, uint64_t ticket, hiccl_comm_t comm);
+/* Retire finished requests (frees their slots and budget); non-blocking. */
+int hiccl_server_progress(hiccl_server_t srv);
+/* done = 1 once the request has finished; device_us = its time on the
+ * device, launch to completion, from stream events. */
+int hiccl_server_poll(hiccl_server_t srv, uint64_t ticket, int* done, double* device_us);
+/* Block until every launched request has finished and retire them. */
+int hiccl_server_drain(hiccl_server_t srv);
+/* Bytes currently charged and requests currently running. */
+int hiccl_server_usage(hiccl_server_t srv, size_t* used_bytes, int* running);
+int hiccl_server_destroy(hiccl_server_t srv);
+
+/* --------------------------------------------------------- payload formats */
+
+/* Convert `n` float32 values to the payload format on the device, in
+ * stream order: bf16 (round to nearest even) into `out` (uint16 bits), or
+ * e4m3 codes into `out` with one power-of-two float32 scale per 256
+ * elements into `scales` (n must be a multiple of 256). */
+int hiccl_to_payload(int dtype, const float* in, void* out, float* scales, size_t n, void* stream);
+/* Widen a payload back to float32 on the device. */
+int hiccl_from_payload(int dtype, const void* in, const float* scales, float* out, size_t n, void* stream);
+
+/* ------------------------------------------------------------------- misc */
+
+const char* hiccl_last_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int hiccl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HICCL_H */

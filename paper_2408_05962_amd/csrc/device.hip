@@ -1,0 +1,1033 @@
+// Device side of the executor for gfx950: task-table upload, the tile
+// kernels (16-byte vector copy; fused k-operand elementwise reduce for
+// int32 / float32 / bf16 / fp8-with-scales), the persistent executor whose
+// dependency progress lives in device counters, the one-launch-per-stage
+// form, batching, the autotuner, the serving loop and payload conversions.
+//
+// Method: HiCCL (arXiv 2408.05962). A stage of Sec. 4.5 is a set of
+// point-to-point transfers optionally followed by a reduction computation;
+// here each transfer is a copy between virtual-rank buffers in HBM and each
+// reduction node is one fused pass over its operands. Execution needs no
+// global barrier (Sec. 5.2): a task starts when the tasks it depends on have
+// retired, tracked with per-task counters.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+
+#include "hiccl_impl.hpp"
+
+namespace hiccl {
+
+// ------------------------------------------------------------ task table
+// 128-byte descriptor. meta = kind | op << 2 | dtype << 4 | nsrc << 8.
+// With more than four operands, src[0] / src_sc[0] point at arrays of
+// operand addresses in device memory.
+struct alignas(16) DevTask {
+  uint64_t dst, dst_sc;
+  uint64_t src[4], src_sc[4];
+  uint64_t count;
+  uint64_t tile_elems;
+  uint32_t meta;
+  uint32_t npred;
+  uint32_t succ_begin, nsucc;
+  uint32_t first_tile, ntiles;
+  uint32_t comm, pad;
+};
+static_assert(sizeof(DevTask) == 128, "descriptor size");
+
+constexpr int kCtlWords = 16;  // claim, exit, abort, status, t0 lo/hi, ...
+enum { CTL_CLAIM = 0, CTL_EXIT = 1, CTL_ABORT = 2, CTL_STATUS = 3 };
+
+struct ExecArgs {
+  const DevTask* tasks;
+  const uint32_t* tile_task;
+  const uint32_t* succ;
+  uint32_t* pending;        // per task: retired predecessors this run
+  uint32_t* done;           // per task: retired tiles this run
+  uint32_t* comm_left;      // per collective: tasks not yet retired
+  const uint32_t* comm_ntasks;
+  uint32_t* ctl;
+  unsigned long long* times;  // [ncomm] completion stamps, [ncomm] = start stamp
+  uint32_t ntiles, ntasks, ncomm, spin_limit;
+};
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return fail(HICCL_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));        \
+  } while (0)
+
+// ------------------------------------------------------------ element codecs
+__device__ __forceinline__ float bf16lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+__device__ __forceinline__ uint32_t to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest, ties to even
+  return u >> 16;
+}
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi) { return to_bf16(lo) | (to_bf16(hi) << 16); }
+
+// OCP e4m3: 1 sign, 4 exponent (bias 7), 3 fraction bits; 448 largest finite.
+__device__ __forceinline__ float dec_e4m3(uint32_t c) {
+  uint32_t e = (c >> 3) & 0xFu, m = c & 7u;
+  float v = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : float(m) * 0.001953125f;
+  return (c & 0x80u) ? -v : v;
+}
+__device__ __forceinline__ uint32_t enc_e4m3(float x) {
+  uint32_t s = (__float_as_uint(x) >> 24) & 0x80u;
+  float a = fabsf(x);
+  if (a >= 448.f) return s | 0x7Eu;
+  if (a < 0.015625f) return s | uint32_t(__float2int_rn(a * 512.f));   // subnormals, step 2^-9
+  uint32_t u = __float_as_uint(a);
+  int e = int(u >> 23) - 127;
+  uint32_t q = (u >> 20) & 7u, rem = u & 0xFFFFFu;
+  if (rem > 0x80000u || (rem == 0x80000u && (q & 1u))) ++q;   // round to nearest, ties to even
+  if (q == 8u) {
+    q = 0;
+    ++e;
+  }
+  uint32_t code = (uint32_t(e + 7) << 3) | q;
+  return s | (code > 0x7Eu ? 0x7Eu : code);
+}
+// exponent e of the least power-of-two scale with amax <= 448 * 2^e
+__device__ __forceinline__ int scale_exp(float amax) {
+  if (amax == 0.f) return 0;
+  int ex;
+  float f = frexpf(amax, &ex);
+  int e = f <= 0.875f ? ex - 9 : ex - 8;
+  return e < -126 ? -126 : (e > 127 ? 127 : e);
+}
+
+// ------------------------------------------------------------ tile kernels
+constexpr int kUnroll = 4;
+
+// 16-byte global accesses with the streaming (non-temporal) cache hint:
+// every byte of a task is touched once per task, so it is not kept in cache.
+#ifndef HICCL_STREAMING
+#define HICCL_STREAMING 1
+#endif
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint4 ld16(const uint4* p) {
+#if HICCL_STREAMING
+  v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+#else
+  return *p;
+#endif
+}
+__device__ __forceinline__ void st16(uint4* p, uint4 x) {
+#if HICCL_STREAMING
+  v4u v = {x.x, x.y, x.z, x.w};
+  __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(p));
+#else
+  *p = x;
+#endif
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void copy_bytes(const uint8_t* __restrict__ s, uint8_t* __restrict__ d, uint64_t nb) {
+  const int tid = threadIdx.x;
+  if (((uintptr_t(s) | uintptr_t(d)) & 15u) == 0) {
+    const uint4* sv = reinterpret_cast<const uint4*>(s);
+    uint4* dv = reinterpret_cast<uint4*>(d);
+    uint64_t nv = nb >> 4, i = tid;
+    for (; i + (kUnroll - 1) * BLOCK < nv; i += kUnroll * BLOCK) {
+      uint4 r[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) r[u] = ld16(sv + i + u * BLOCK);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) st16(dv + i + u * BLOCK, r[u]);
+    }
+    for (; i < nv; i += BLOCK) dv[i] = sv[i];
+    for (uint64_t b = (nv << 4) + tid; b < nb; b += BLOCK) d[b] = s[b];
+  } else if (((uintptr_t(s) | uintptr_t(d)) & 3u) == 0) {
+    const uint32_t* sw = reinterpret_cast<const uint32_t*>(s);
+    uint32_t* dw = reinterpret_cast<uint32_t*>(d);
+    uint64_t nw = nb >> 2;
+    for (uint64_t i = tid; i < nw; i += BLOCK) dw[i] = sw[i];
+    for (uint64_t b = (nw << 2) + tid; b < nb; b += BLOCK) d[b] = s[b];
+  } else {
+    for (uint64_t b = tid; b < nb; b += BLOCK) d[b] = s[b];
+  }
+}
+
+// Operand j's data address (element 0 of the task).
+__device__ __forceinline__ uint64_t src_addr(const DevTask* t, int j, int k) {
+  return k <= 4 ? t->src[j] : reinterpret_cast<const uint64_t*>(t->src[0])[j];
+}
+__device__ __forceinline__ uint64_t src_sc_addr(const DevTask* t, int j, int k) {
+  return k <= 4 ? t->src_sc[j] : reinterpret_cast<const uint64_t*>(t->src_sc[0])[j];
+}
+
+// 32-bit lanes: float32 or int32 (two's complement wrap) with sum / max / min.
+template <bool FLT, int OP>
+__device__ __forceinline__ uint32_t op32(uint32_t a, uint32_t b) {
+  if (FLT) {
+    float x = __uint_as_float(a), y = __uint_as_float(b);
+    float r = OP == HICCL_SUM ? x + y : (OP == HICCL_MAX ? fmaxf(x, y) : fminf(x, y));
+    return __float_as_uint(r);
+  }
+  int32_t x = int32_t(a), y = int32_t(b);
+  return OP == HICCL_SUM ? a + b : uint32_t(OP == HICCL_MAX ? max(x, y) : min(x, y));
+}
+template <bool FLT, int OP>
+__device__ __forceinline__ uint4 op32v(uint4 a, uint4 b) {
+  return make_uint4(op32<FLT, OP>(a.x, b.x), op32<FLT, OP>(a.y, b.y), op32<FLT, OP>(a.z, b.z),
+                    op32<FLT, OP>(a.w, b.w));
+}
+
+// Fused reduce of K (compile-time, 0 = runtime k) operands, 32-bit lanes.
+// Operands are combined left to right: ((s0 op s1) op s2) ...
+template <int BLOCK, bool FLT, int OP, int K>
+__device__ __forceinline__ void reduce32(const DevTask* t, int k, uint64_t e0, uint64_t n) {
+  const int tid = threadIdx.x;
+  const int kk = K ? K : k;
+  uint32_t* d = reinterpret_cast<uint32_t*>(t->dst) + e0;
+  bool vec = (uintptr_t(d) & 15u) == 0;
+  for (int j = 0; j < kk; ++j) vec = vec && ((src_addr(t, j, kk) + e0 * 4) & 15u) == 0;
+  uint64_t nv = vec ? n >> 2 : 0;
+  if (nv) {
+    uint4* dv = reinterpret_cast<uint4*>(d);
+    uint64_t i = tid;
+    for (; i + (kUnroll - 1) * BLOCK < nv; i += kUnroll * BLOCK) {
+      uint4 acc[kUnroll];
+      const uint4* s0 = reinterpret_cast<const uint4*>(src_addr(t, 0, kk)) + (e0 >> 2);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) acc[u] = ld16(s0 + i + u * BLOCK);
+      if (K) {
+#pragma unroll
+        for (int j = 1; j < (K ? K : 1); ++j) {
+          const uint4* sj = reinterpret_cast<const uint4*>(src_addr(t, j, kk)) + (e0 >> 2);
+          uint4 v[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) v[u] = ld16(sj + i + u * BLOCK);
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) acc[u] = op32v<FLT, OP>(acc[u], v[u]);
+        }
+      } else {
+        for (int j = 1; j < kk; ++j) {
+          const uint4* sj = reinterpret_cast<const uint4*>(src_addr(t, j, kk)) + (e0 >> 2);
+          uint4 v[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) v[u] = ld16(sj + i + u * BLOCK);
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) acc[u] = op32v<FLT, OP>(acc[u], v[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) st16(dv + i + u * BLOCK, acc[u]);
+    }
+    for (; i < nv; i += BLOCK) {
+      uint4 acc = reinterpret_cast<const uint4*>(src_addr(t, 0, kk))[(e0 >> 2) + i];
+      for (int j = 1; j < kk; ++j)
+        acc = op32v<FLT, OP>(acc, reinterpret_cast<const uint4*>(src_addr(t, j, kk))[(e0 >> 2) + i]);
+      dv[i] = acc;
+    }
+  }
+  for (uint64_t e = (nv << 2) + tid; e < n; e += BLOCK) {
+    uint32_t acc = reinterpret_cast<const uint32_t*>(src_addr(t, 0, kk))[e0 + e];
+    for (int j = 1; j < kk; ++j) acc = op32<FLT, OP>(acc, reinterpret_cast<const uint32_t*>(src_addr(t, j, kk))[e0 + e]);
+    d[e] = acc;
+  }
+}
+
+// bf16 payload: widen to float32, sum left to right, narrow (RNE).
+template <int BLOCK>
+__device__ __forceinline__ void reduce_bf16(const DevTask* t, int k, uint64_t e0, uint64_t n) {
+  const int tid = threadIdx.x;
+  uint16_t* d = reinterpret_cast<uint16_t*>(t->dst) + e0;
+  bool vec = (uintptr_t(d) & 15u) == 0;
+  for (int j = 0; j < k; ++j) vec = vec && ((src_addr(t, j, k) + e0 * 2) & 15u) == 0;
+  uint64_t nv = vec ? n >> 3 : 0;
+  for (uint64_t i = tid; i < nv; i += BLOCK) {
+    float a[8];
+    for (int j = 0; j < k; ++j) {
+      uint4 w = ld16(reinterpret_cast<const uint4*>(src_addr(t, j, k)) + (e0 >> 3) + i);
+      float v[8] = {bf16lo(w.x), bf16hi(w.x), bf16lo(w.y), bf16hi(w.y), bf16lo(w.z), bf16hi(w.z), bf16lo(w.w), bf16hi(w.w)};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = j == 0 ? v[q] : a[q] + v[q];
+    }
+    uint4 o = make_uint4(pack_bf16(a[0], a[1]), pack_bf16(a[2], a[3]), pack_bf16(a[4], a[5]), pack_bf16(a[6], a[7]));
+    st16(reinterpret_cast<uint4*>(d) + i, o);
+  }
+  for (uint64_t e = (nv << 3) + tid; e < n; e += BLOCK) {
+    float a = 0.f;
+    for (int j = 0; j < k; ++j) {
+      float v = __uint_as_float(uint32_t(reinterpret_cast<const uint16_t*>(src_addr(t, j, k))[e0 + e]) << 16);
+      a = j == 0 ? v : a + v;
+    }
+    d[e] = uint16_t(to_bf16(a));
+  }
+}
+
+// fp8 payload with one power-of-two scale per 256 elements. Each lane owns
+// 16 consecutive codes; the 16 lanes of a block find its amax with
+// cross-lane exchanges, pick the new scale, and lane 0 of the group stores
+// it. Counts and offsets are whole blocks, so a group is never split.
+template <int BLOCK>
+__device__ __forceinline__ void reduce_fp8(const DevTask* t, int k, uint64_t e0, uint64_t n) {
+  const int tid = threadIdx.x;
+  uint8_t* d = reinterpret_cast<uint8_t*>(t->dst) + e0;
+  float* dsc = reinterpret_cast<float*>(t->dst_sc) + e0 / 256;
+  uint64_t nv = n >> 4;                     // 16-code vectors; blocks are whole
+  uint64_t nv_round = (nv + BLOCK - 1) / BLOCK * BLOCK;
+  for (uint64_t i = tid; i < nv_round; i += BLOCK) {
+    bool live = i < nv;
+    float a[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) a[q] = 0.f;
+    if (live) {
+      for (int j = 0; j < k; ++j) {
+        uint4 w = ld16(reinterpret_cast<const uint4*>(src_addr(t, j, k) + e0) + i);
+        float sc = reinterpret_cast<const float*>(src_sc_addr(t, j, k))[e0 / 256 + (i >> 4)];
+        uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          float v = dec_e4m3((ws[q >> 2] >> ((q & 3) * 8)) & 0xFFu) * sc;
+          a[q] = j == 0 ? v : a[q] + v;
+        }
+      }
+    }
+    float amax = 0.f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) amax = fmaxf(amax, fabsf(a[q]));
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 16));
+    int e = scale_exp(amax);
+    if (live) {
+      uint32_t o[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < 16; ++q) o[q >> 2] |= enc_e4m3(ldexpf(a[q], -e)) << ((q & 3) * 8);
+      st16(reinterpret_cast<uint4*>(d) + i, make_uint4(o[0], o[1], o[2], o[3]));
+      if ((i & 15u) == 0) dsc[i >> 4] = amax == 0.f ? 1.f : ldexpf(1.f, e);
+    }
+  }
+}
+
+template <int BLOCK>
+__device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t tile) {
+  const uint32_t meta = t->meta;
+  const int kind = meta & 3, op = (meta >> 2) & 3, dt = (meta >> 4) & 15, k = int(meta >> 8);
+  const uint64_t e0 = uint64_t(tile - t->first_tile) * t->tile_elems;
+  const uint64_t e1 = min(e0 + t->tile_elems, t->count);
+  const uint64_t n = e1 - e0;
+  if (kind == kCopy) {
+    const uint64_t es = dt == HICCL_BFLOAT16 ? 2 : (dt == HICCL_FP8_E4M3 ? 1 : 4);
+    copy_bytes<BLOCK>(reinterpret_cast<const uint8_t*>(t->src[0]) + e0 * es, reinterpret_cast<uint8_t*>(t->dst) + e0 * es,
+                      n * es);
+    if (dt == HICCL_FP8_E4M3) {
+      const float* ss = reinterpret_cast<const float*>(t->src_sc[0]) + e0 / 256;
+      float* ds = reinterpret_cast<float*>(t->dst_sc) + e0 / 256;
+      for (uint64_t b = threadIdx.x; b < n / 256; b += BLOCK) ds[b] = ss[b];
+    }
+    return;
+  }
+  if (dt == HICCL_FLOAT32) {
+    if (op == HICCL_SUM) {
+      switch (k) {
+        case 2: reduce32<BLOCK, true, HICCL_SUM, 2>(t, k, e0, n); break;
+        case 3: reduce32<BLOCK, true, HICCL_SUM, 3>(t, k, e0, n); break;
+        case 4: reduce32<BLOCK, true, HICCL_SUM, 4>(t, k, e0, n); break;
+        default: reduce32<BLOCK, true, HICCL_SUM, 0>(t, k, e0, n); break;
+      }
+    } else if (op == HICCL_MAX) {
+      reduce32<BLOCK, true, HICCL_MAX, 0>(t, k, e0, n);
+    } else {
+      reduce32<BLOCK, true, HICCL_MIN, 0>(t, k, e0, n);
+    }
+  } else if (dt == HICCL_INT32) {
+    if (op == HICCL_SUM) {
+      switch (k) {
+        case 2: reduce32<BLOCK, false, HICCL_SUM, 2>(t, k, e0, n); break;
+        case 4: reduce32<BLOCK, false, HICCL_SUM, 4>(t, k, e0, n); break;
+        default: reduce32<BLOCK, false, HICCL_SUM, 0>(t, k, e0, n); break;
+      }
+    } else if (op == HICCL_MAX) {
+      reduce32<BLOCK, false, HICCL_MAX, 0>(t, k, e0, n);
+    } else {
+      reduce32<BLOCK, false, HICCL_MIN, 0>(t, k, e0, n);
+    }
+  } else if (dt == HICCL_BFLOAT16) {
+    reduce_bf16<BLOCK>(t, k, e0, n);
+  } else {
+    reduce_fp8<BLOCK>(t, k, e0, n);
+  }
+}
+
+__device__ __forceinline__ unsigned long long dev_clock() { return wall_clock64(); }
+
+// Retire one tile of task `k`: the last tile to finish releases the
+// task's successors and, when it is its collective's last task, stamps the
+// completion time. Called by one thread after the workgroup barrier.
+__device__ __forceinline__ void retire(const ExecArgs& a, const DevTask* t, uint32_t k) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // publish this workgroup's stores device-wide
+  uint32_t old = __hip_atomic_fetch_add(&a.done[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (old + 1 != t->ntiles) return;
+  // last tile of the task: take in the other tiles' releases, then release the successors
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+  const uint32_t b = t->succ_begin, e = b + t->nsucc;
+  for (uint32_t s = b; s < e; ++s)
+    __hip_atomic_fetch_add(&a.pending[a.succ[s]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (a.times) {
+    uint32_t left = __hip_atomic_fetch_sub(&a.comm_left[t->comm], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (left == 1) a.times[t->comm] = dev_clock();
+  }
+}
+
+// Persistent executor: workgroups claim tiles in table order (a topological
+// order), wait until the tile's task has all predecessors retired, run
+// it, and retire it. Claiming in topological order guarantees progress: a
+// waiting tile only depends on tiles claimed earlier by running workgroups.
+// The wait is bounded; on expiry the run is aborted and every workgroup
+// exits. The last workgroup to leave resets the counters for the next run.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void hiccl_persistent(ExecArgs a) {
+  __shared__ uint32_t s_tile, s_flag;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) {
+      uint32_t tl = __hip_atomic_fetch_add(&a.ctl[CTL_CLAIM], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      uint32_t flag = 0;
+      if (tl == 0 && a.times) a.times[a.ncomm] = dev_clock();
+      if (tl < a.ntiles) {
+        uint32_t k = a.tile_task[tl];
+        uint32_t need = a.tasks[k].npred;
+        uint32_t polls = 0;
+        // poll with relaxed device-coherent loads; one acquire fence once the wait is over
+        while (need && __hip_atomic_load(&a.pending[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          if (__hip_atomic_load(&a.ctl[CTL_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            flag = 1;
+            break;
+          }
+          if (++polls >= a.spin_limit) {
+            __hip_atomic_store(&a.ctl[CTL_ABORT], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.ctl[CTL_STATUS], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            flag = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      s_tile = tl;
+      s_flag = flag;
+    }
+    __syncthreads();
+    const uint32_t tl = s_tile;
+    if (tl >= a.ntiles || s_flag) break;
+    const uint32_t k = __builtin_amdgcn_readfirstlane(a.tile_task[tl]);
+    const DevTask* t = a.tasks + k;
+    run_tile<BLOCK>(t, tl);
+    __syncthreads();
+    if (tid == 0) retire(a, t, k);
+  }
+  __syncthreads();   // every wave has read s_tile / s_flag before they are reused below
+  if (tid == 0) {
+    uint32_t old = __hip_atomic_fetch_add(&a.ctl[CTL_EXIT], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_flag = (old + 1 == gridDim.x) ? 2u : 0u;
+  }
+  __syncthreads();
+  if (s_flag == 2u) {
+    for (uint32_t i = tid; i < a.ntasks; i += BLOCK) {
+      a.pending[i] = 0;
+      a.done[i] = 0;
+    }
+    for (uint32_t i = tid; i < a.ncomm; i += BLOCK) a.comm_left[i] = a.comm_ntasks[i];
+    __syncthreads();
+    if (tid == 0) {
+      a.ctl[CTL_CLAIM] = 0;
+      a.ctl[CTL_ABORT] = 0;
+      a.ctl[CTL_EXIT] = 0;
+      __threadfence();
+    }
+  }
+}
+
+// One launch per dependency stage: the kernel boundary orders the stages,
+// so no counters are used.
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void hiccl_staged(ExecArgs a, uint32_t lo, uint32_t hi) {
+  for (uint32_t tl = lo + blockIdx.x; tl < hi; tl += gridDim.x) {
+    const uint32_t k = __builtin_amdgcn_readfirstlane(a.tile_task[tl]);
+    run_tile<BLOCK>(a.tasks + k, tl);
+  }
+}
+
+constexpr int kBlock = 256;
+
+// ------------------------------------------------------------- executable
+// An uploaded task table: one communicator, or a merged batch.
+struct Exe {
+  int device = -1;
+  DevTask* d_tasks = nullptr;
+  uint32_t* d_tile_task = nullptr;
+  uint32_t* d_succ = nullptr;
+  uint64_t* d_extra = nullptr;
+  uint32_t* d_cnt = nullptr;           // pending | done | comm_left | ctl
+  uint32_t* d_comm_ntasks = nullptr;
+  unsigned long long* d_times = nullptr;
+  uint32_t ntasks = 0, ntiles = 0, ncomm = 0;
+  std::vector<uint32_t> stage_tile_begin;
+  int mode = HICCL_EXEC_PERSISTENT;
+  int grid = 0;
+  uint32_t spin_limit = 1u << 22;
+
+  ExecArgs args() const {
+    ExecArgs a;
+    a.tasks = d_tasks;
+    a.tile_task = d_tile_task;
+    a.succ = d_succ;
+    a.pending = d_cnt;
+    a.done = d_cnt + ntasks;
+    a.comm_left = d_cnt + 2 * size_t(ntasks);
+    a.comm_ntasks = d_comm_ntasks;
+    a.ctl = d_cnt + 2 * size_t(ntasks) + ncomm;
+    a.times = d_times;
+    a.ntiles = ntiles;
+    a.ntasks = ntasks;
+    a.ncomm = ncomm;
+    a.spin_limit = spin_limit;
+    return a;
+  }
+  void free_all() {
+    if (device >= 0) {
+      int cur = 0;
+      (void)hipGetDevice(&cur);
+      (void)hipSetDevice(device);
+      (void)hipDeviceSynchronize();
+      (void)hipFree(d_tasks);
+      (void)hipFree(d_tile_task);
+      (void)hipFree(d_succ);
+      (void)hipFree(d_extra);
+      (void)hipFree(d_cnt);
+      (void)hipFree(d_comm_ntasks);
+      (void)hipFree(d_times);
+      (void)hipSetDevice(cur);
+    }
+    *this = Exe();
+  }
+};
+
+struct DeviceState {
+  Exe exe;
+  void* ws = nullptr;
+  bool own_ws = false;
+  hipEvent_t ev = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool launched = false;
+};
+
+void device_state_free(DeviceState* s) {
+  if (!s) return;
+  s->exe.free_all();
+  if (s->own_ws && s->ws) (void)hipFree(s->ws);
+  if (s->ev) (void)hipEventDestroy(s->ev);
+  delete s;
+}
+
+static int device_grid(int want) {
+  static int cached = 0;
+  if (!cached) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(hiccl_persistent<kBlock>),
+                                                     kBlock, 0) != hipSuccess)
+      per = 4;
+    cached = std::max(1, cus * std::max(1, per));
+  }
+  return want > 0 ? want : cached;
+}
+
+// Flatten plans into one device task table. ws_base[i] is plan i's workspace.
+static int upload(const std::vector<const Plan*>& plans, const std::vector<uint64_t>& ws_base, int mode, int grid,
+                  uint32_t spin_limit, bool with_times, Exe& ex) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  ex.device = dev;
+  ex.mode = mode;
+  ex.spin_limit = spin_limit;
+  ex.ncomm = uint32_t(plans.size());
+  // merged order: by stage, then collective, then the plan's own order
+  struct Ref {
+    uint32_t plan, idx;
+  };
+  std::vector<Ref> refs;
+  for (uint32_t p = 0; p < plans.size(); ++p)
+    for (uint32_t i = 0; i < plans[p]->tasks.size(); ++i) refs.push_back({p, i});
+  if (plans.size() > 1)
+    std::stable_sort(refs.begin(), refs.end(), [&](const Ref& x, const Ref& y) {
+      return plans[x.plan]->tasks[x.idx].stage < plans[y.plan]->tasks[y.idx].stage;
+    });
+  std::vector<std::vector<uint32_t>> newidx(plans.size());
+  for (uint32_t p = 0; p < plans.size(); ++p) newidx[p].resize(plans[p]->tasks.size());
+  for (uint32_t i = 0; i < refs.size(); ++i) newidx[refs[i].plan][refs[i].idx] = i;
+
+  size_t nt = refs.size();
+  std::vector<DevTask> h(nt);
+  std::vector<uint32_t> succ, tile_task, comm_n(plans.size(), 0);
+  std::vector<uint64_t> extra;
+  std::vector<std::pair<size_t, size_t>> extra_fix;   // (task, offset into extra) to patch
+  int nstages = 0;
+  for (size_t i = 0; i < nt; ++i) {
+    const Task& t = plans[refs[i].plan]->tasks[refs[i].idx];
+    const uint64_t wsb = ws_base[refs[i].plan];
+    auto addr = [&](const Loc& l) { return l.space == 0 ? l.addr : wsb + l.addr; };
+    auto saddr = [&](const Loc& l) { return l.space == 0 ? l.scales : wsb + l.scales; };
+    DevTask& d = h[i];
+    std::memset(&d, 0, sizeof(d));
+    d.dst = addr(t.dst);
+    d.dst_sc = t.dtype == HICCL_FP8_E4M3 ? saddr(t.dst) : 0;
+    size_t k = t.src.size();
+    if (k <= 4) {
+      for (size_t j = 0; j < k; ++j) {
+        d.src[j] = addr(t.src[j]);
+        d.src_sc[j] = t.dtype == HICCL_FP8_E4M3 ? saddr(t.src[j]) : 0;
+      }
+    } else {
+      extra_fix.push_back({i, extra.size()});
+      for (size_t j = 0; j < k; ++j) extra.push_back(addr(t.src[j]));
+      for (size_t j = 0; j < k; ++j) extra.push_back(t.dtype == HICCL_FP8_E4M3 ? saddr(t.src[j]) : 0);
+    }
+    d.count = t.count;
+    d.tile_elems = t.tile_elems;
+    d.meta = uint32_t(t.kind) | uint32_t(t.op) << 2 | uint32_t(t.dtype) << 4 | uint32_t(k) << 8;
+    d.npred = uint32_t(t.preds.size());
+    d.succ_begin = uint32_t(succ.size());
+    d.nsucc = uint32_t(t.succs.size());
+    for (int s : t.succs) succ.push_back(newidx[refs[i].plan][s]);
+    d.first_tile = uint32_t(tile_task.size());
+    d.ntiles = t.ntiles;
+    d.comm = refs[i].plan;
+    for (uint32_t q = 0; q < t.ntiles; ++q) tile_task.push_back(uint32_t(i));
+    comm_n[refs[i].plan] += 1;
+    nstages = std::max(nstages, t.stage + 1);
+  }
+  ex.ntasks = uint32_t(nt);
+  ex.ntiles = uint32_t(tile_task.size());
+  // stage boundaries in the merged table (stage-sorted when one plan is stage-ordered or several are merged)
+  ex.stage_tile_begin.assign(nstages + 1, ex.ntiles);
+  for (int i = int(nt) - 1; i >= 0; --i) {
+    const Task& t = plans[refs[i].plan]->tasks[refs[i].idx];
+    ex.stage_tile_begin[t.stage] = h[i].first_tile;
+  }
+  for (int s = nstages - 1; s >= 0; --s) ex.stage_tile_begin[s] = std::min(ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1]);
+
+  auto alloc_copy = [&](void** dptr, const void* src, size_t bytes) -> int {
+    HIP_TRY(hipMalloc(dptr, std::max<size_t>(bytes, 16)));
+    if (bytes) HIP_TRY(hipMemcpy(*dptr, src, bytes, hipMemcpyHostToDevice));
+    return 0;
+  };
+  if (!extra.empty()) {
+    if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_extra), extra.data(), extra.size() * 8)) return rc;
+    for (auto& f : extra_fix) {
+      size_t k = h[f.first].meta >> 8;
+      h[f.first].src[0] = uint64_t(reinterpret_cast<uintptr_t>(ex.d_extra + f.second));
+      h[f.first].src_sc[0] = uint64_t(reinterpret_cast<uintptr_t>(ex.d_extra + f.second + k));
+    }
+  }
+  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_tasks), h.data(), h.size() * sizeof(DevTask))) return rc;
+  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_tile_task), tile_task.data(), tile_task.size() * 4)) return rc;
+  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_succ), succ.data(), succ.size() * 4)) return rc;
+  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_comm_ntasks), comm_n.data(), comm_n.size() * 4)) return rc;
+  size_t ncnt = 2 * nt + plans.size() + kCtlWords;
+  std::vector<uint32_t> cnt(ncnt, 0);
+  for (size_t p = 0; p < plans.size(); ++p) cnt[2 * nt + p] = comm_n[p];
+  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_cnt), cnt.data(), cnt.size() * 4)) return rc;
+  if (with_times) {
+    HIP_TRY(hipMalloc(reinterpret_cast<void**>(&ex.d_times), (plans.size() + 1) * sizeof(unsigned long long)));
+    HIP_TRY(hipMemset(ex.d_times, 0, (plans.size() + 1) * sizeof(unsigned long long)));
+  }
+  ex.grid = std::min<int>(device_grid(grid), std::max<uint32_t>(1u, ex.ntiles));
+  return 0;
+}
+
+static int launch(const Exe& ex, hipStream_t st) {
+  if (ex.ntiles == 0) return 0;
+  ExecArgs a = ex.args();
+  if (ex.mode == HICCL_EXEC_PERSISTENT) {
+    hipLaunchKernelGGL(hiccl_persistent<kBlock>, dim3(ex.grid), dim3(kBlock), 0, st, a);
+  } else {
+    for (size_t s = 0; s + 1 < ex.stage_tile_begin.size(); ++s) {
+      uint32_t lo = ex.stage_tile_begin[s], hi = ex.stage_tile_begin[s + 1];
+      if (hi <= lo) continue;
+      int g = int(std::min<uint32_t>(hi - lo, uint32_t(device_grid(0) * 2)));
+      hipLaunchKernelGGL(hiccl_staged<kBlock>, dim3(g), dim3(kBlock), 0, st, a, lo, hi);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
+static int read_status(const Exe& ex, int* status) {
+  uint32_t st = 0;
+  uint32_t* ctl = ex.d_cnt + 2 * size_t(ex.ntasks) + ex.ncomm;
+  HIP_TRY(hipMemcpy(&st, ctl + CTL_STATUS, 4, hipMemcpyDeviceToHost));
+  if (st) {
+    uint32_t z = 0;
+    HIP_TRY(hipMemcpy(ctl + CTL_STATUS, &z, 4, hipMemcpyHostToDevice));
+  }
+  *status = int(st);
+  return 0;
+}
+
+// Make sure a communicator's tables and workspace are on the device.
+static int ensure_device(Comm& c) {
+  if (c.dev) return 0;
+  auto* s = new DeviceState;
+  uint64_t ws = 0;
+  if (c.plan.ws_bytes) {
+    if (c.user_ws) {
+      s->ws = c.user_ws;
+    } else {
+      hipError_t e = hipMalloc(&s->ws, c.plan.ws_bytes);
+      if (e != hipSuccess) {
+        delete s;
+        return fail(e == hipErrorOutOfMemory ? HICCL_ERR_OOM : HICCL_ERR_HIP,
+                    std::string("workspace allocation: ") + hipGetErrorString(e));
+      }
+      s->own_ws = true;
+    }
+    ws = uint64_t(reinterpret_cast<uintptr_t>(s->ws));
+  }
+  int rc = upload({&c.plan}, {ws}, c.exec.mode, c.exec.grid, c.exec.spin_limit, false, s->exe);
+  if (!rc && hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) != hipSuccess)
+    rc = fail(HICCL_ERR_HIP, "event creation failed");
+  if (rc) {
+    device_state_free(s);
+    return rc;
+  }
+  c.dev = s;
+  return 0;
+}
+
+}  // namespace hiccl
+
+using namespace hiccl;
+
+extern "C" {
+
+int hiccl_run(hiccl_comm_t comm, void* stream) {
+  if (!comm) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator");
+  Comm& c = comm->c;
+  if (!c.planned) return fail(HICCL_ERR_STATE, "call hiccl_init before hiccl_run");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (c.dev && c.dev->launched && c.dev->last_stream != st && hipEventQuery(c.dev->ev) == hipErrorNotReady)
+    return fail(HICCL_ERR_STATE, "a run of this communicator is in flight on another stream");
+  if (int rc = ensure_device(c)) return rc;
+  if (int rc = launch(c.dev->exe, st)) return rc;
+  HIP_TRY(hipEventRecord(c.dev->ev, st));
+  c.dev->last_stream = st;
+  c.dev->launched = true;
+  return HICCL_SUCCESS;
+}
+
+int hiccl_wait(hiccl_comm_t comm) {
+  if (!comm) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator");
+  Comm& c = comm->c;
+  if (!c.dev || !c.dev->launched) return HICCL_SUCCESS;
+  HIP_TRY(hipEventSynchronize(c.dev->ev));
+  int status = 0;
+  if (int rc = read_status(c.dev->exe, &status)) return rc;
+  if (status) return fail(HICCL_ERR_TIMEOUT, "executor gave up a dependency wait (spin limit reached)");
+  return HICCL_SUCCESS;
+}
+
+}  // extern "C"
+
+// ================================================================ batching
+struct hiccl_batch_s {
+  std::vector<hiccl_comm_t> comms;
+  int mode = HICCL_BATCH_PERSISTENT;
+  Exe merged;                    // persistent form
+  std::vector<Exe> each;         // graph / serial forms (per collective, with completion stamps)
+  hipStream_t cap = nullptr;     // capture stream of the graph form
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t ev = nullptr;
+  bool launched = false;
+  double clock_hz = 1e8;
+};
+
+namespace hiccl {
+static int batch_prepare(hiccl_batch_s* b) {
+  std::vector<const Plan*> plans;
+  std::vector<uint64_t> wsb;
+  for (hiccl_comm_t c : b->comms) {
+    if (int rc = ensure_device(c->c)) return rc;
+    plans.push_back(&c->c.plan);
+    wsb.push_back(uint64_t(reinterpret_cast<uintptr_t>(c->c.dev->ws)));
+  }
+  const ExecCfg& x = b->comms[0]->c.exec;
+  if (b->mode == HICCL_BATCH_PERSISTENT) {
+    if (int rc = upload(plans, wsb, HICCL_EXEC_PERSISTENT, x.grid, x.spin_limit, true, b->merged)) return rc;
+  } else {
+    b->each.resize(plans.size());
+    for (size_t i = 0; i < plans.size(); ++i) {
+      const ExecCfg& xi = b->comms[i]->c.exec;
+      if (int rc = upload({plans[i]}, {wsb[i]}, xi.mode, xi.grid, xi.spin_limit, true, b->each[i])) return rc;
+    }
+  }
+  int dev = 0, khz = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+    b->clock_hz = double(khz) * 1e3;
+  HIP_TRY(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
+  return 0;
+}
+}  // namespace hiccl
+
+extern "C" {
+
+int hiccl_batch_create(const hiccl_comm_t* comms, int n, int mode, hiccl_batch_t* out) {
+  if (!comms || n < 1 || !out) return fail(HICCL_ERR_INVALID_ARG, "batch needs at least one communicator");
+  if (mode < HICCL_BATCH_PERSISTENT || mode > HICCL_BATCH_SERIAL) return fail(HICCL_ERR_INVALID_ARG, "bad batch mode");
+  for (int i = 0; i < n; ++i) {
+    if (!comms[i]) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator in batch");
+    if (!comms[i]->c.planned) return fail(HICCL_ERR_STATE, "batch members must be initialized");
+  }
+  auto* b = new hiccl_batch_s;
+  b->comms.assign(comms, comms + n);
+  b->mode = mode;
+  if (int rc = batch_prepare(b)) {
+    hiccl_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return HICCL_SUCCESS;
+}
+
+int hiccl_batch_run(hiccl_batch_t b, void* stream) {
+  if (!b) return fail(HICCL_ERR_INVALID_ARG, "NULL batch");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (b->mode == HICCL_BATCH_PERSISTENT) {
+    if (int rc = launch(b->merged, st)) return rc;
+  } else if (b->mode == HICCL_BATCH_SERIAL) {
+    for (const Exe& e : b->each)
+      if (int rc = launch(e, st)) return rc;
+  } else {
+    if (!b->gexec) {
+      HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+      HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+      for (const Exe& e : b->each)
+        if (int rc = launch(e, b->cap)) {
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(b->cap, &g);
+          if (g) (void)hipGraphDestroy(g);
+          return rc;
+        }
+      HIP_TRY(hipStreamEndCapture(b->cap, &b->graph));
+      HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+    }
+    HIP_TRY(hipGraphLaunch(b->gexec, st));
+  }
+  HIP_TRY(hipEventRecord(b->ev, st));
+  b->launched = true;
+  return HICCL_SUCCESS;
+}
+
+int hiccl_batch_wait(hiccl_batch_t b) {
+  if (!b) return fail(HICCL_ERR_INVALID_ARG, "NULL batch");
+  if (!b->launched) return HICCL_SUCCESS;
+  HIP_TRY(hipEventSynchronize(b->ev));
+  int bad = 0;
+  if (b->mode == HICCL_BATCH_PERSISTENT) {
+    int s = 0;
+    if (int rc = read_status(b->merged, &s)) return rc;
+    bad |= s;
+  } else {
+    for (const Exe& e : b->each) {
+      int s = 0;
+      if (int rc = read_status(e, &s)) return rc;
+      bad |= s;
+    }
+  }
+  if (bad) return fail(HICCL_ERR_TIMEOUT, "executor gave up a dependency wait (spin limit reached)");
+  return HICCL_SUCCESS;
+}
+
+int hiccl_batch_times(hiccl_batch_t b, uint64_t* ns, int n) {
+  if (!b || !ns || n != int(b->comms.size())) return fail(HICCL_ERR_INVALID_ARG, "bad batch times request");
+  std::vector<unsigned long long> stamp(n), start;
+  if (b->mode == HICCL_BATCH_PERSISTENT) {
+    std::vector<unsigned long long> t(n + 1);
+    HIP_TRY(hipMemcpy(t.data(), b->merged.d_times, (n + 1) * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i) stamp[i] = t[i];
+    start.push_back(t[n]);
+  } else {
+    for (int i = 0; i < n; ++i) {
+      unsigned long long t[2];
+      HIP_TRY(hipMemcpy(t, b->each[i].d_times, sizeof(t), hipMemcpyDeviceToHost));
+      stamp[i] = t[0];
+      start.push_back(t[1]);
+    }
+  }
+  unsigned long long t0 = *std::min_element(start.begin(), start.end());
+  for (int i = 0; i < n; ++i)
+    ns[i] = stamp[i] >= t0 ? uint64_t(double(stamp[i] - t0) * 1e9 / b->clock_hz) : 0;
+  return HICCL_SUCCESS;
+}
+
+int hiccl_batch_destroy(hiccl_batch_t b) {
+  if (!b) return HICCL_SUCCESS;
+  if (b->launched) (void)hipEventSynchronize(b->ev);
+  b->merged.free_all();
+  for (Exe& e : b->each) e.free_all();
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->ev) (void)hipEventDestroy(b->ev);
+  delete b;
+  return HICCL_SUCCESS;
+}
+
+// =============================================================== autotuner
+int hiccl_autotune(hiccl_comm_t comm, const int* stripes, int nstripes, const int* pipes, int npipes,
+                   const size_t* tiles, int ntiles, int reps, void* stream, int* best_stripe, int* best_pipe,
+                   size_t* best_tile, double* best_us) {
+  if (!comm) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator");
+  if (!stripes || !pipes || !tiles || nstripes < 1 || npipes < 1 || ntiles < 1 || reps < 1)
+    return fail(HICCL_ERR_INVALID_ARG, "empty candidate set");
+  Comm& c = comm->c;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  double best = -1;
+  int bs = c.stripe, bp = c.pipe;
+  size_t bt = c.exec.tile_bytes;
+  for (int a = 0; a < nstripes; ++a)
+    for (int p = 0; p < npipes; ++p)
+      for (int q = 0; q < ntiles; ++q) {
+        hiccl_set_stripe(comm, stripes[a]);
+        hiccl_set_pipeline(comm, pipes[p]);
+        hiccl_set_exec(comm, c.exec.mode, tiles[q], c.exec.grid, c.exec.order);
+        if (hiccl_init(comm) != HICCL_SUCCESS) continue;
+        if (hiccl_run(comm, stream) != HICCL_SUCCESS) continue;
+        std::vector<float> ms;
+        bool ok = true;
+        for (int r = 0; r < reps && ok; ++r) {
+          ok = hipEventRecord(e0, st) == hipSuccess && hiccl_run(comm, stream) == HICCL_SUCCESS &&
+               hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+          float t = 0;
+          if (ok && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms.push_back(t);
+        }
+        if (!ok || ms.empty() || hiccl_wait(comm) != HICCL_SUCCESS) continue;
+        std::sort(ms.begin(), ms.end());
+        double med = ms[ms.size() / 2] * 1e3;
+        if (best < 0 || med < best) {
+          best = med;
+          bs = stripes[a];
+          bp = pipes[p];
+          bt = tiles[q];
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  hiccl_set_stripe(comm, bs);
+  hiccl_set_pipeline(comm, bp);
+  hiccl_set_exec(comm, c.exec.mode, bt, c.exec.grid, c.exec.order);
+  int rc = hiccl_init(comm);
+  if (rc) return rc;
+  if (best < 0) return fail(HICCL_ERR_INVALID_ARG, "no candidate could be run");
+  if (best_stripe) *best_stripe = bs;
+  if (best_pipe) *best_pipe = bp;
+  if (best_tile) *best_tile = bt;
+  if (best_us) *best_us = best;
+  return HICCL_SUCCESS;
+}
+
+}  // extern "C"
+
+// ========================================================= payload formats
+namespace hiccl {
+
+__global__ void k_to_bf16(const float* __restrict__ in, uint16_t* __restrict__ out, size_t n) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    out[i] = uint16_t(to_bf16(in[i]));
+}
+__global__ void k_from_bf16(const uint16_t* __restrict__ in, float* __restrict__ out, size_t n) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    out[i] = __uint_as_float(uint32_t(in[i]) << 16);
+}
+// one 256-element block per 16 lanes, 16 elements per lane
+__global__ void k_to_fp8(const float* __restrict__ in, uint8_t* __restrict__ out, float* __restrict__ scales,
+                         size_t nblocks) {
+  const size_t nv = nblocks * 16;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t base = blockIdx.x * size_t(blockDim.x); base < nv; base += stride) {
+    size_t i = base + threadIdx.x;
+    bool live = i < nv;
+    float a[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) a[q] = live ? in[i * 16 + q] : 0.f;
+    float amax = 0.f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) amax = fmaxf(amax, fabsf(a[q]));
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 16));
+    int e = scale_exp(amax);
+    if (live) {
+      uint32_t o[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < 16; ++q) o[q >> 2] |= enc_e4m3(ldexpf(a[q], -e)) << ((q & 3) * 8);
+      reinterpret_cast<uint4*>(out)[i] = make_uint4(o[0], o[1], o[2], o[3]);
+      if ((i & 15u) == 0) scales[i >> 4] = amax == 0.f ? 1.f : ldexpf(1.f, e);
+    }
+  }
+}
+__global__ void k_from_fp8(const uint8_t* __restrict__ in, const float* __restrict__ scales, float* __restrict__ out,
+                           size_t n) {
+  for (size_t i = blockIdx.x * size_t(blockDim.x) + threadIdx.x; i < n; i += size_t(gridDim.x) * blockDim.x)
+    out[i] = dec_e4m3(in[i]) * scales[i / 256];
+}
+
+}  // namespace hiccl
+
+extern "C" {
+
+int hiccl_to_payload(int dtype, const float* in, void* out, float* scales, size_t n, void* stream) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (n == 0) return HICCL_SUCCESS;
+  if (!in || !out) return fail(HICCL_ERR_INVALID_ARG, "NULL buffer");
+  int g = int(std::min<size_t>((n + 255) / 256, 8192));
+  if (dtype == HICCL_BFLOAT16) {
+    hipLaunchKernelGGL(k_to_bf16, dim3(g), dim3(256), 0, st, in, static_cast<uint16_t*>(out), n);
+  } else if (dtype == HICCL_FP8_E4M3) {
+    if (n % 256 || !scales) return fail(HICCL_ERR_INVALID_ARG, "fp8 needs whole 256-element blocks and scales");
+    if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15u)
+      return fail(HICCL_ERR_INVALID_ARG, "fp8 conversion needs 16-byte aligned buffers");
+    int gb = int(std::min<size_t>((n / 16 + 255) / 256, 8192));
+    hipLaunchKernelGGL(k_to_fp8, dim3(gb), dim3(256), 0, st, in, static_cast<uint8_t*>(out), scales, n / 256);
+  } else {
+    return fail(HICCL_ERR_INVALID_ARG, "payload conversion is for bf16 and fp8");
+  }
+  HIP_TRY(hipGetLastError());
+  return HICCL_SUCCESS;
+}
+
+int hiccl_from_payload(int dtype, const void* in, const float* scales, float* out, size_t n, void* stream) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (n == 0) return HICCL_SUCCESS;
+  if (!in || !out) return fail(HICCL_ERR_INVALID_ARG, "NULL buffer");
+  int g = int(std::min<size_t>((n + 255) / 256, 8192));
+  if (dtype == HICCL_BFLOAT16) {
+    hipLaunchKernelGGL(k_from_bf16, dim3(g), dim3(256), 0, st, static_cast<const uint16_t*>(in), out, n);
+  } else if (dtype == HICCL_FP8_E4M3) {
+    if (n % 256 || !scales) return fail(HICCL_ERR_INVALID_ARG, "fp8 needs whole 256-element blocks and scales");
+    hipLaunchKernelGGL(k_from_fp8, dim3(g), dim3(256), 0, st, static_cast<const uint8_t*>(in), scales, out, n);
+  } else {
+    return fail(HICCL_ERR_INVALID_ARG, "payload conversion is for bf16 and fp8");
+  }
+  HIP_TRY(hipGetLastError());
+  return HICCL_SUCCESS;
+}
+
+}  // extern "C"

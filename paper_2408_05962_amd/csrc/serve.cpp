@@ -1,0 +1,169 @@
+// Serving loop support: admission under a device-memory budget and a fixed
+// number of concurrent slots (one stream each), so that requests arriving
+// while others execute are admitted as soon as a slot and budget free up
+// and their work overlaps on the device (continuous batching).
+#include <hip/hip_runtime.h>
+
+#include <unordered_map>
+#include <vector>
+
+#include "hiccl_impl.hpp"
+
+using namespace hiccl;
+
+struct hiccl_server_s {
+  struct Req {
+    int slot = -1;
+    size_t footprint = 0;
+    bool launched = false, done = false;
+    hipEvent_t start = nullptr, stop = nullptr;
+    double device_us = 0;
+  };
+  size_t budget = 0, used = 0;
+  std::vector<hipStream_t> streams;
+  std::vector<int64_t> slot_owner;     // ticket or -1
+  std::unordered_map<uint64_t, Req> reqs;
+  uint64_t next = 1;
+};
+
+#define HIP_OK(expr, what)                                                         \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess) return fail(HICCL_ERR_HIP, std::string(what) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+static void release(hiccl_server_s* s, uint64_t ticket, hiccl_server_s::Req& r) {
+  if (r.slot >= 0 && s->slot_owner[r.slot] == int64_t(ticket)) s->slot_owner[r.slot] = -1;
+  s->used -= r.footprint;
+  r.footprint = 0;
+  r.slot = -1;
+}
+
+extern "C" {
+
+int hiccl_server_create(size_t hbm_budget, int slots, hiccl_server_t* out) {
+  if (!out || slots < 1 || hbm_budget == 0) return fail(HICCL_ERR_INVALID_ARG, "bad server parameters");
+  auto* s = new hiccl_server_s;
+  s->budget = hbm_budget;
+  for (int i = 0; i < slots; ++i) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      hiccl_server_destroy(s);
+      return fail(HICCL_ERR_HIP, "stream creation failed");
+    }
+    s->streams.push_back(st);
+    s->slot_owner.push_back(-1);
+  }
+  *out = s;
+  return HICCL_SUCCESS;
+}
+
+int hiccl_server_admit(hiccl_server_t s, size_t footprint, uint64_t* ticket) {
+  if (!s || !ticket) return fail(HICCL_ERR_INVALID_ARG, "NULL argument");
+  if (footprint > s->budget) return fail(HICCL_ERR_INVALID_ARG, "request footprint exceeds the whole budget");
+  if (s->used + footprint > s->budget) return fail(HICCL_ERR_BUSY, "not enough budget free");
+  int slot = -1;
+  for (size_t i = 0; i < s->slot_owner.size(); ++i)
+    if (s->slot_owner[i] < 0) {
+      slot = int(i);
+      break;
+    }
+  if (slot < 0) return fail(HICCL_ERR_BUSY, "no slot free");
+  uint64_t t = s->next++;
+  hiccl_server_s::Req r;
+  r.slot = slot;
+  r.footprint = footprint;
+  s->slot_owner[slot] = int64_t(t);
+  s->used += footprint;
+  s->reqs[t] = r;
+  *ticket = t;
+  return HICCL_SUCCESS;
+}
+
+int hiccl_server_stream(hiccl_server_t s, uint64_t ticket, void** stream) {
+  if (!s || !stream) return fail(HICCL_ERR_INVALID_ARG, "NULL argument");
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end() || it->second.slot < 0) return fail(HICCL_ERR_INVALID_ARG, "unknown or finished ticket");
+  *stream = s->streams[it->second.slot];
+  return HICCL_SUCCESS;
+}
+
+int hiccl_server_launch(hiccl_server_t s, uint64_t ticket, hiccl_comm_t comm) {
+  if (!s || !comm) return fail(HICCL_ERR_INVALID_ARG, "NULL argument");
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end() || it->second.slot < 0 || it->second.launched)
+    return fail(HICCL_ERR_STATE, "ticket is not admitted or already launched");
+  auto& r = it->second;
+  hipStream_t st = s->streams[r.slot];
+  HIP_OK(hipEventCreate(&r.start), "event");
+  HIP_OK(hipEventCreate(&r.stop), "event");
+  HIP_OK(hipEventRecord(r.start, st), "event record");
+  int rc = hiccl_run(comm, st);
+  if (rc) return rc;
+  HIP_OK(hipEventRecord(r.stop, st), "event record");
+  r.launched = true;
+  return HICCL_SUCCESS;
+}
+
+int hiccl_server_progress(hiccl_server_t s) {
+  if (!s) return fail(HICCL_ERR_INVALID_ARG, "NULL server");
+  for (auto& kv : s->reqs) {
+    auto& r = kv.second;
+    if (!r.launched || r.done) continue;
+    hipError_t q = hipEventQuery(r.stop);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return fail(HICCL_ERR_HIP, std::string("request failed: ") + hipGetErrorString(q));
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) r.device_us = ms * 1e3;
+    r.done = true;
+    release(s, kv.first, r);
+    (void)hipEventDestroy(r.start);
+    (void)hipEventDestroy(r.stop);
+    r.start = r.stop = nullptr;
+  }
+  return HICCL_SUCCESS;
+}
+
+int hiccl_server_poll(hiccl_server_t s, uint64_t ticket, int* done, double* device_us) {
+  if (!s) return fail(HICCL_ERR_INVALID_ARG, "NULL server");
+  if (int rc = hiccl_server_progress(s)) return rc;
+  auto it = s->reqs.find(ticket);
+  if (it == s->reqs.end()) return fail(HICCL_ERR_INVALID_ARG, "unknown ticket");
+  if (done) *done = it->second.done ? 1 : 0;
+  if (device_us) *device_us = it->second.device_us;
+  if (it->second.done) s->reqs.erase(it);
+  return HICCL_SUCCESS;
+}
+
+int hiccl_server_drain(hiccl_server_t s) {
+  if (!s) return fail(HICCL_ERR_INVALID_ARG, "NULL server");
+  for (hipStream_t st : s->streams) HIP_OK(hipStreamSynchronize(st), "stream sync");
+  return hiccl_server_progress(s);
+}
+
+int hiccl_server_usage(hiccl_server_t s, size_t* used_bytes, int* running) {
+  if (!s) return fail(HICCL_ERR_INVALID_ARG, "NULL server");
+  if (used_bytes) *used_bytes = s->used;
+  if (running) {
+    int n = 0;
+    for (int64_t o : s->slot_owner) n += o >= 0;
+    *running = n;
+  }
+  return HICCL_SUCCESS;
+}
+
+int hiccl_server_destroy(hiccl_server_t s) {
+  if (!s) return HICCL_SUCCESS;
+  for (hipStream_t st : s->streams) {
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+  }
+  for (auto& kv : s->reqs) {
+    if (kv.second.start) (void)hipEventDestroy(kv.second.start);
+    if (kv.second.stop) (void)hipEventDestroy(kv.second.stop);
+  }
+  delete s;
+  return HICCL_SUCCESS;
+}
+
+}  // extern "C"

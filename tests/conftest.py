@@ -11,6 +11,13 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+    mark = config.getoption("-m") or ""
+    if "gpu" in mark and "not gpu" not in mark:
+        # bring up torch and the device before any per-test time limit starts
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+            torch.zeros(1, device="cuda").sum().item()
 
 
 def gpu_available() -> bool:

@@ -1,0 +1,254 @@
+"""The C-ABI library on the CPU: exports, argument and state errors, and the
+factorizer's plans against the paper's worked examples and the oracle's
+per-level byte counts. No kernel is launched here."""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import tree as OT
+from tests import harness as H
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLD = os.path.join(ROOT, "tests", "golden")
+
+
+@pytest.fixture(scope="module")
+def hc():
+    from paper_2408_05962_amd import hiccl
+    try:
+        hiccl.lib()
+    except ImportError as e:
+        pytest.skip(str(e))
+    return hiccl
+
+
+def test_every_declared_symbol_is_exported(hc):
+    with open(os.path.join(ROOT, "include", "hiccl.h")) as f:
+        text = f.read()
+    names = set(re.findall(r"^\s*(?:int|const char\*)\s+(hiccl_[a-z_0-9]+)\s*\(", text, re.M))
+    assert len(names) >= 35
+    lib = hc.lib()
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert lib.hiccl_version() >= 10000
+
+
+def _bufs(p, n, dtype=np.float32):
+    return [np.zeros(n, dtype) for _ in range(p)]
+
+
+def _code(fn, *a):
+    from paper_2408_05962_amd.hiccl import HicclError
+    try:
+        fn(*a)
+    except HicclError as e:
+        return e.code
+    return 0
+
+
+def test_argument_and_state_errors(hc):
+    import ctypes as C
+    lib = hc.lib()
+    h = C.c_void_p()
+    assert lib.hiccl_comm_create(0, 1, C.byref(h)) == hc.ERR_INVALID_ARG
+    assert lib.hiccl_comm_create(4, 9, C.byref(h)) == hc.ERR_INVALID_ARG
+    assert lib.hiccl_init(None) == hc.ERR_INVALID_ARG
+    c = hc.Comm(4, "float32")
+    s, r = _bufs(4, 8), _bufs(4, 8)
+    assert _code(c.set_hierarchy, [2, 3]) == hc.ERR_INVALID_ARG          # product != nranks
+    assert _code(c.add_multicast, s, r, 8, 0, [1, 1]) == hc.ERR_INVALID_ARG   # duplicate leaf
+    assert _code(c.add_multicast, s, r, 8, 4, [1]) == hc.ERR_INVALID_ARG      # root out of range
+    assert _code(c.add_multicast, s, r, 8, 0, [7]) == hc.ERR_INVALID_ARG      # leaf out of range
+    assert _code(c.run) == hc.ERR_STATE                                       # not initialized
+    c.add_multicast(s, r, 8, 0, [1, 2])
+    # a second primitive writing rank 2's receive buffer in the same step is a race ...
+    assert _code(c.add_multicast, s, r, 8, 3, [2]) == hc.ERR_RACE
+    # ... and reading a buffer the step writes is a race too
+    assert _code(c.add_multicast, r, s, 8, 1, [3]) == hc.ERR_RACE
+    c.add_fence()
+    c.add_multicast(s, r, 8, 3, [2])                                         # fine after a fence
+    c.set_hierarchy([2, 2])
+    c.set_stripe(3)
+    assert _code(c.init) == hc.ERR_INVALID_ARG                               # 3 divides no group of {2,2}
+    c.set_stripe(2)
+    c.init()
+    assert _code(c.add_fence) == hc.ERR_STATE
+    assert _code(c.add_multicast, s, r, 8, 0, [1]) == hc.ERR_STATE
+    assert _code(c.init) == hc.ERR_STATE
+    c.set_pipeline(2)                                                        # re-plans
+    c.init()
+    assert c.plan_info()["ntasks"] > 0
+    c.close()
+
+
+def test_payload_type_errors(hc):
+    c = hc.Comm(2, "fp8_e4m3")
+    d = [np.zeros(512, np.uint8) for _ in range(2)]
+    sc = [np.ones(2, np.float32) for _ in range(2)]
+    bufs = list(zip(d, sc))
+    assert _code(c.add_multicast, bufs, bufs[::-1], 100, 0, [1]) == hc.ERR_INVALID_ARG   # not whole blocks
+    assert _code(c.add_multicast, d, d[::-1], 256, 0, [1]) == hc.ERR_INVALID_ARG         # scales missing
+    assert _code(c.add_reduction, bufs, [bufs[1], bufs[0]], 256, [0, 1], 0, "max") == hc.ERR_UNSUPPORTED
+    c.add_reduction([bufs[0], bufs[1]], [(np.zeros(256, np.uint8), np.ones(1, np.float32))] * 2, 256, [0, 1], 0)
+    c.close()
+    b = hc.Comm(2, "bfloat16")
+    x = [np.zeros(8, np.uint16) for _ in range(4)]
+    assert _code(b.add_reduction, x[:2], x[2:], 8, [0, 1], 0, "min") == hc.ERR_UNSUPPORTED
+    b.close()
+
+
+def test_ring_length_is_validated(hc):
+    c = hc.Comm(4, "float32")
+    s, r = _bufs(4, 4), _bufs(4, 4)
+    c.add_multicast(s, r, 4, 0, [1, 2, 3])
+    c.set_hierarchy([2, 2])
+    c.set_ring(3)
+    assert _code(c.init) in (hc.ERR_INVALID_ARG, hc.ERR_UNSUPPORTED)
+    c.close()
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def _bcast_plan(hc, h, s=1, m=1, root=0, n=96):
+    p = int(np.prod(h))
+    send, recv = _bufs(p, n), _bufs(p, n)
+    c = hc.Comm(p, "float32")
+    c.add_multicast(send, recv, n, root, list(range(p)))
+    c.set_hierarchy(h)
+    c.set_stripe(s)
+    c.set_pipeline(m)
+    c.init()
+    return c
+
+
+def test_library_reproduces_worked_broadcast(hc):
+    g = _gold("broadcast_2x2x3_tree.json")
+    c = _bcast_plan(hc, g["hierarchy"])
+    hops = {}
+    for t in c.plan_tasks():
+        a, b = t["src_rank"][0], t["dst_rank"]
+        if a != b:
+            hops.setdefault(str(OT.depth(a, b, g["hierarchy"])), []).append([a, b])
+    for k, v in g["hops_by_depth"].items():
+        assert sorted(hops[k]) == sorted(v)
+    # the local root copy has no predecessor; the leaf hops wait for their staging rank (3 stages)
+    assert c.plan_info()["nstages"] == g["stages_unstriped"]
+    c.close()
+
+
+def test_library_reproduces_striped_broadcast(hc):
+    g = _gold("broadcast_2x2x3_striped.json")
+    c = _bcast_plan(hc, g["hierarchy"], s=g["stripes"], n=96)
+    tasks = c.plan_tasks()
+    # the scatter hops carry stripes 1 and 2 from the root to their owners (stripe 0 stays at the root)
+    scat = sorted([t["src_rank"][0], t["dst_rank"]] for t in tasks if t["stage"] == 0 and t["src_rank"][0] == 0
+                  and t["stripe"] > 0 and t["dst_rank"] == g["owners"][t["stripe"]])
+    assert scat == g["scatter_hops"]
+    assert c.plan_info()["nstages"] == g["stages_striped"]
+    c.close()
+    # with at least as many channels as stages every channel can be in flight at once
+    c = _bcast_plan(hc, g["hierarchy"], s=g["stripes"], m=g["min_channels_full_overlap"], n=96 * 4)
+    chans = {t["channel"] for t in c.plan_tasks() if t["stage"] == 0}
+    assert chans == set(range(g["min_channels_full_overlap"]))
+    c.close()
+
+
+def test_direct_vs_hierarchical_cross_node_copies(hc):
+    g = _gold("broadcast_direct_vs_hierarchical_2x3.json")
+    for key, hier in (("cross_node_copies_direct", g["direct_hierarchy"]),
+                      ("cross_node_copies_hierarchical", g["hierarchical_hierarchy"])):
+        c = _bcast_plan(hc, hier, n=64)
+        lb, _, _ = c.query_bytes(g["accounting_hierarchy"])
+        assert lb[1] == g[key] * 64 * 4
+        c.close()
+
+
+def test_listing_allreduce_fine_grain_dependencies(hc):
+    """Three ranks: each in-place multicast M_i waits for its reduction R_i only, not for a barrier."""
+    g = _gold("allreduce_listing_3ranks.json")
+    from paper_2408_05962_amd import collectives as CO
+    p, d = g["p"], 8
+    send, recv = _bufs(p, d * p), _bufs(p, d * p)
+    c = CO.make("all_reduce", p, "float32", send, recv, d, hierarchy=[p])
+    tasks = c.plan_tasks()
+    red = [t for t in tasks if t["step"] == 0]
+    mc = [t for t in tasks if t["step"] == 1]
+    assert [t["kind"] for t in red] == [1] * p and len(mc) == p * (p - 1)
+    assert all(t["npred"] == 1 for t in mc)            # exactly the reduction of the same chunk
+    for t in mc:
+        assert t["src_rank"][0] == red[t["prim"] - p]["dst_rank"]
+    c.close()
+
+
+COLL = ["broadcast", "reduce", "all_gather", "reduce_scatter", "all_reduce", "all_to_all", "scatter", "gather"]
+
+
+@pytest.mark.parametrize("h,s", [([2, 4, 2], 1), ([2, 4, 2], 4), ([2, 2, 3], 3), ([4, 4], 2), ([2, 4], 1)])
+@pytest.mark.parametrize("name", COLL)
+def test_level_bytes_match_oracle(hc, name, h, s):
+    """Per-level logical bytes of the library's factorization equal the oracle's, and the top level
+    carries exactly the minimum implied by Table 3."""
+    from paper_2408_05962_amd import collectives as CO
+    p = int(np.prod(h))
+    d = 16 * s
+    send = _bufs(p, H.send_len(name, p, d))
+    recv = _bufs(p, H.recv_len(name, p, d))
+    c = CO.make(name, p, "float32", send, recv, d, hierarchy=h, stripe=s, pipeline=3)
+    lb, rd, wr = c.query_bytes()
+    c.close()
+    ref = OT.collective_level_bytes(name, h, d, s=s, esize=4, align=4)
+    assert lb[1:len(h) + 1] == ref[1:], (lb, ref)
+    assert lb[1] == OT.min_top_bytes(name, p, p // h[0], d) * 4
+
+
+@pytest.mark.parametrize("name,coef", [("broadcast", 32), ("reduce", 38.5), ("all_gather", 32),
+                                       ("reduce_scatter", 38.5), ("all_reduce", 68.5), ("all_to_all", 44)])
+def test_executed_bytes_config2_shape(hc, name, coef):
+    """Executed device-memory bytes of the {2,4,2}, s = 4 schedules as multiples of the per-rank buffer S."""
+    from paper_2408_05962_amd import collectives as CO
+    p, h, s, m = 16, [2, 4, 2], 4, 8
+    d = 4096
+    S = d * p * 4
+    send = _bufs(p, H.send_len(name, p, d))
+    recv = _bufs(p, H.recv_len(name, p, d))
+    c = CO.make(name, p, "float32", send, recv, d, hierarchy=h, stripe=s, pipeline=m)
+    _, rd, wr = c.query_bytes()
+    c.close()
+    assert (rd + wr) == coef * S
+
+
+def test_tree_reduction_traffic(hc):
+    """A full-leaf reduction on {2,4,2} reads 26 n and writes 11 n (8 + 2 + 1 fused nodes)."""
+    p, n = 16, 64
+    send, recv = _bufs(p, n), _bufs(p, n)
+    c = hc.Comm(p, "float32")
+    c.add_reduction(send, recv, n, list(range(p)), 0)
+    c.set_hierarchy([2, 4, 2])
+    c.init()
+    _, rd, wr = c.query_bytes()
+    ks = sorted(t["nsrc"] for t in c.plan_tasks())
+    c.close()
+    assert rd == 26 * n * 4 and wr == 11 * n * 4
+    assert ks == [2] * 9 + [4] * 2
+
+
+def test_workspace_and_plan_info(hc):
+    from paper_2408_05962_amd import collectives as CO
+    p, d = 16, 1024
+    send, recv = _bufs(p, d * p), _bufs(p, d)
+    c = CO.make("reduce_scatter", p, "float32", send, recv, d, hierarchy=[2, 4, 2], stripe=4, pipeline=8,
+                tile_bytes=4096)
+    info = c.plan_info()
+    assert c.workspace_size() == info["workspace_bytes"] > 0
+    assert info["tile_elems"] == 1024
+    assert info["ntiles"] >= info["ntasks"]
+    tasks = c.plan_tasks()
+    assert all(t["stage"] == 0 or t["npred"] > 0 for t in tasks)
+    assert [t["stage"] for t in tasks] == sorted(t["stage"] for t in tasks)   # claim order is stage order
+    c.close()

@@ -1,0 +1,170 @@
+"""GPU parity: the HIP executor against the CPU oracle, through the C ABI."""
+import zlib
+
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from tests import harness as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_2408_05962_amd import hiccl
+    hiccl.lib()          # must load: a GPU run without the native library is a failure, not a skip
+    return torch
+
+
+def _host_inputs(name, p, d, dtype, seed):
+    rng = np.random.default_rng(seed)
+    n = H.send_len(name, p, d)
+    if dtype == "int32":
+        return [rng.integers(-1000, 1001, n).astype(np.int32) for _ in range(p)]
+    return [rng.standard_normal(n).astype(np.float32) for _ in range(p)]
+
+
+def _run(torch, name, p, h, dtype, d, s=1, m=1, mode="persistent", sends=None, seed=0, reps=1, tile=0, root=0,
+         op="sum", order="stage"):
+    from paper_2408_05962_amd import collectives as CO
+    if sends is None:
+        sends = _host_inputs(name, p, d, dtype, seed)
+    tdt = torch.int32 if dtype == "int32" else torch.float32
+    S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+    R = torch.full((p, H.recv_len(name, p, d)), -7, dtype=tdt, device="cuda")
+    send = [S[r] for r in range(p)]
+    recv = [R[r] for r in range(p)]
+    c = CO.make(name, p, dtype, send, recv, d, hierarchy=h, stripe=s, pipeline=m, exec_mode=mode, tile_bytes=tile,
+                root=root, op=op, order=order)
+    c.set_spin_limit(1 << 20)    # a stalled dependency fails the test within seconds
+    st = torch.cuda.current_stream()
+    outs = []
+    for _ in range(reps):
+        R.fill_(-7)
+        c.run(st)
+        c.wait()
+        torch.cuda.synchronize()
+        outs.append(R.cpu().numpy().copy())
+    c.close()
+    return sends, outs
+
+
+def _got(name, out, p, root):
+    exp_ranks = [root] if name in ("reduce", "gather") else range(p)
+    return {r: out[r] for r in exp_ranks}
+
+
+def test_config1_allreduce_int32_bit_exact(torch_cuda):
+    """All-Reduce over 4 ranks as {2,2}, 65,536 int32 per rank in [-1000, 1000], s = m = 1."""
+    import synth
+    p, n = 4, 65536
+    sends = [synth.rank_buffer("int32", 0, 0, r, n) for r in range(p)]
+    for mode in ("persistent", "staged"):
+        _, outs = _run(torch_cuda, "all_reduce", p, [2, 2], "int32", n // p, sends=sends, reps=3, mode=mode)
+        for out in outs:
+            H.check_result("all_reduce", _got("all_reduce", out, p, 0), sends, "int32")
+
+
+@pytest.mark.parametrize("name", H.EIGHT)
+@pytest.mark.parametrize("dtype", ["int32", "float32"])
+@pytest.mark.parametrize("h,s,m", [([2, 4, 2], 4, 8), ([2, 3], 3, 2), ([4, 4], 2, 3), ([16], 1, 1), ([2, 2, 2, 2], 2, 1)])
+def test_collectives_small(torch_cuda, name, dtype, h, s, m):
+    p = int(np.prod(h))
+    d = 1003 if name not in ("all_gather", "gather") else 2051   # ragged: not a multiple of the vector width
+    sends, outs = _run(torch_cuda, name, p, h, dtype, d, s=s, m=m, seed=zlib.crc32(f"{name}{dtype}{h}".encode()) % 1000,
+                       reps=2, tile=4096)
+    for out in outs:
+        H.check_result(name, _got(name, out, p, 0), sends, dtype, h=h, s=s)
+    assert np.array_equal(outs[0], outs[1])   # re-runs reset their counters and reproduce bit for bit
+
+
+@pytest.mark.parametrize("name", H.SIX)
+def test_staged_matches_persistent(torch_cuda, name):
+    h, s, m = [2, 4, 2], 4, 4
+    p = 16
+    sends, a = _run(torch_cuda, name, p, h, "float32", 4096, s=s, m=m, seed=5, mode="persistent", tile=8192)
+    _, b = _run(torch_cuda, name, p, h, "float32", 4096, s=s, m=m, sends=sends, mode="staged", tile=8192)
+    _, c = _run(torch_cuda, name, p, h, "float32", 4096, s=s, m=m, sends=sends, mode="persistent", tile=8192,
+                order="program")
+    assert np.array_equal(a[0].view(np.uint32), b[0].view(np.uint32))
+    assert np.array_equal(a[0].view(np.uint32), c[0].view(np.uint32))
+
+
+@pytest.mark.parametrize("op", ["max", "min"])
+@pytest.mark.parametrize("dtype", ["int32", "float32"])
+def test_max_min(torch_cuda, op, dtype):
+    for name in ("all_reduce", "reduce_scatter", "reduce"):
+        sends, outs = _run(torch_cuda, name, 8, [2, 4], dtype, 777, s=2, m=2, op=op, seed=3)
+        H.check_result(name, _got(name, outs[0], 8, 0), sends, dtype, op=op)
+
+
+def test_root_and_odd_hierarchies(torch_cuda):
+    for name in ("broadcast", "reduce", "scatter", "gather"):
+        for root in (5, 11):
+            sends, outs = _run(torch_cuda, name, 12, [2, 2, 3], "int32", 513, s=3, m=2, root=root, seed=root)
+            H.check_result(name, _got(name, outs[0], 12, root), sends, "int32", root=root)
+
+
+def test_empty_and_tiny(torch_cuda):
+    for name in ("all_reduce", "all_to_all", "broadcast"):
+        sends, outs = _run(torch_cuda, name, 4, [2, 2], "float32", 1, s=2, m=4, seed=1)
+        H.check_result(name, _got(name, outs[0], 4, 0), sends, "float32", h=[2, 2], s=2)
+    from paper_2408_05962_amd import Comm
+    import torch
+    x = torch.zeros(4, device="cuda")
+    c = Comm(4, "float32")
+    c.add_multicast([x] * 4, [x] * 4, 0, 0, [1, 2, 3])   # count 0: a no-op
+    c.set_hierarchy([2, 2])
+    c.init()
+    c.run()
+    c.wait()
+    assert c.plan_info()["ntasks"] == 0
+
+
+def test_many_reruns_stress(torch_cuda):
+    """Many small tasks, many repeats: device counters reset themselves and ordering holds."""
+    import torch
+    from paper_2408_05962_amd import collectives as CO
+    p, d = 16, 2048
+    sends = _host_inputs("all_reduce", p, d, "int32", 11)
+    S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+    R = torch.zeros((p, d * p), dtype=torch.int32, device="cuda")
+    c = CO.make("all_reduce", p, "int32", [S[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=[2, 4, 2],
+                stripe=4, pipeline=8, tile_bytes=1024)
+    exp = H.expected("all_reduce", sends)[0]
+    st = torch.cuda.current_stream()
+    for it in range(50):
+        R.zero_()
+        c.run(st)
+    c.wait()
+    got = R.cpu().numpy()
+    for r in range(p):
+        assert np.array_equal(got[r], exp)
+    c.close()
+
+
+@pytest.mark.parametrize("name", H.SIX)
+def test_config2_full_size(torch_cuda, name):
+    """Six collectives, 16 ranks as {2,4,2}, 64 MiB float32 per rank ~ N(0,1), stripe 4, pipeline 8 (bench launch)."""
+    import torch
+    import synth
+    from paper_2408_05962_amd import collectives as CO
+    p, h, s, m = 16, [2, 4, 2], 4, 8
+    S_el = 64 * 2 ** 20 // 4
+    d = S_el // p
+    sl, rl = H.send_len(name, p, d), H.recv_len(name, p, d)
+    Sd = synth.device_buffers("float32", 2000 + H.SIX.index(name), p, sl)
+    R = torch.full((p, rl), float("nan"), device="cuda")
+    c = CO.make(name, p, "float32", [Sd[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=h, stripe=s,
+                pipeline=m)
+    sends = [x for x in Sd.cpu().numpy()]
+    c.run(torch.cuda.current_stream())
+    c.wait()
+    torch.cuda.synchronize()
+    got = R.cpu().numpy()
+    c.close()
+    H.check_result(name, _got(name, got, p, 0), sends, "float32", h=h, s=s, order_exact=True)

@@ -1,0 +1,95 @@
+"""The library's plans executed on host memory by its schedule checker, against the oracle.
+
+The checker runs each plan in several random dependency-respecting orders
+with poisoned workspace, so a missing dependency edge fails here on the CPU.
+"""
+import zlib
+
+import numpy as np
+import pytest
+
+from tests import harness as H
+
+pytest.importorskip("ctypes")
+
+
+def _lib():
+    from paper_2408_05962_amd import hiccl
+    try:
+        hiccl.lib()
+    except ImportError as e:
+        pytest.skip(str(e))
+    return hiccl
+
+
+def _inputs(name, p, d, dtype, seed):
+    rng = np.random.default_rng(seed)
+    n = H.send_len(name, p, d)
+    if dtype == "int32":
+        return [rng.integers(-1000, 1001, n).astype(np.int32) for _ in range(p)]
+    return [rng.standard_normal(n).astype(np.float32) for _ in range(p)]
+
+
+def host_run(name, p, h, dtype, d, s=1, m=1, root=0, op="sum", seed=0, norders=3, tile=0, form="listing"):
+    _lib()
+    from paper_2408_05962_amd import collectives as CO
+    sends = _inputs(name, p, d, dtype, seed)
+    recvs = [np.full(H.recv_len(name, p, d), -7, H.NP[dtype]) for _ in range(p)]
+    c = CO.make(name, p, dtype, sends, recvs, d, hierarchy=h, stripe=s, pipeline=m, root=root, op=op, tile_bytes=tile,
+                form=form)
+    c.validate_host(seed=seed, norders=norders)
+    info = c.plan_info()
+    c.close()
+    exp_ranks = [root] if name in ("reduce", "gather") else range(p)
+    return sends, {r: recvs[r] for r in exp_ranks}, info
+
+
+@pytest.mark.parametrize("name", H.EIGHT)
+@pytest.mark.parametrize("dtype", ["int32", "float32"])
+@pytest.mark.parametrize("h,s,m", [([2, 4, 2], 4, 8), ([2, 3], 3, 2), ([4, 4], 2, 3), ([16], 1, 1),
+                                   ([2, 2, 2, 2], 2, 1), ([2, 2], 1, 1)])
+def test_plans_match_oracle(name, dtype, h, s, m):
+    p = int(np.prod(h))
+    d = 37 if name not in ("all_gather", "gather") else 61
+    seed = zlib.crc32(f"{name}{dtype}{h}".encode()) % 1000
+    sends, got, _ = host_run(name, p, h, dtype, d, s=s, m=m, seed=seed)
+    H.check_result(name, got, sends, dtype, h=h, s=s)
+
+
+@pytest.mark.parametrize("op", ["max", "min"])
+def test_max_min_plans(op):
+    for name in ("all_reduce", "reduce_scatter", "reduce"):
+        for dtype in ("int32", "float32"):
+            sends, got, _ = host_run(name, 8, [2, 4], dtype, 33, s=2, m=2, op=op, seed=4)
+            H.check_result(name, got, sends, dtype, op=op)
+
+
+def test_roots_and_sparse_hierarchy():
+    for name in ("broadcast", "reduce", "scatter", "gather"):
+        for root in (5, 11):
+            sends, got, _ = host_run(name, 12, [2, 2, 3], "int32", 29, s=3, m=2, root=root, seed=root)
+            H.check_result(name, got, sends, "int32", root=root)
+
+
+def test_single_step_allreduce_form():
+    sends, got, _ = host_run("all_reduce", 8, [2, 4], "float32", 16, s=2, m=2, form="single")
+    H.check_result("all_reduce", got, sends, "float32", order_exact=False)
+
+
+def test_config1_shape():
+    """All-Reduce of 4 ranks as {2,2}, 65,536 int32 per rank: 4 stages (RS node, RS top, AG top, AG leaf)."""
+    import synth
+    _lib()
+    from paper_2408_05962_amd import collectives as CO
+    p, n = 4, 65536
+    sends = [synth.rank_buffer("int32", 0, 0, r, n) for r in range(p)]
+    recvs = [np.zeros(n, np.int32) for _ in range(p)]
+    c = CO.make("all_reduce", p, "int32", sends, recvs, n // p, hierarchy=[2, 2])
+    c.validate_host(seed=9, norders=3)
+    info = c.plan_info()
+    lb, rd, wr = c.query_bytes()
+    c.close()
+    H.check_result("all_reduce", dict(enumerate(recvs)), sends, "int32")
+    assert info["nstages"] == 4
+    assert lb[1] == 512 * 1024 and lb[2] == 1024 * 1024      # top 512 KiB, intra-node 1 MiB
+    assert rd + wr == 15 * n * 4                              # 15 S executed bytes
