@@ -178,6 +178,13 @@ int hiccl_run(hiccl_comm_t comm, void* stream);
  * reused. Returns TIMEOUT if the executor gave up a dependency wait. */
 int hiccl_wait(hiccl_comm_t comm);
 
+/* Tile claiming of the persistent executor (not a paper parameter): the
+ * task table is dealt round-robin into `queues` queues (1..8; 0 = 8), each
+ * claimed `batch` tiles per atomic (0 = 4). A single queue keeps progress
+ * independent of how many workgroups are resident at once (use it when
+ * other kernels share the device); several queues cut counter contention. */
+int hiccl_set_claim(hiccl_comm_t comm, int queues, int batch);
+
 /* Bounded-wait budget of the persistent executor, in polls of a dependency
  * counter (default 2^22, a few seconds). Expiry aborts the run cleanly:
  * every workgroup exits and hiccl_wait returns TIMEOUT. */

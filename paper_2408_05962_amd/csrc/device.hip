@@ -41,8 +41,15 @@ struct alignas(16) DevTask {
 };
 static_assert(sizeof(DevTask) == 128, "descriptor size");
 
-constexpr int kCtlWords = 16;  // claim, exit, abort, status, t0 lo/hi, ...
-enum { CTL_CLAIM = 0, CTL_EXIT = 1, CTL_ABORT = 2, CTL_STATUS = 3 };
+// Control block: one claim counter per tile queue, each on its own 128-byte
+// line, then the exit / abort / status words.
+constexpr int kMaxQueues = 8;
+constexpr int kLine = 32;                      // words per 128-byte line
+constexpr int kCtlWords = (kMaxQueues + 1) * kLine;
+enum { CTL_EXIT = kMaxQueues * kLine, CTL_ABORT = CTL_EXIT + 1, CTL_STATUS = CTL_EXIT + 2 };
+#ifndef HICCL_CLAIM_BATCH
+#define HICCL_CLAIM_BATCH 4
+#endif
 
 struct ExecArgs {
   const DevTask* tasks;
@@ -55,6 +62,8 @@ struct ExecArgs {
   uint32_t* ctl;
   unsigned long long* times;  // [ncomm] completion stamps, [ncomm] = start stamp
   uint32_t ntiles, ntasks, ncomm, spin_limit;
+  uint32_t queues;            // tile queues (tile t belongs to queue t % queues)
+  uint32_t batch;             // tiles claimed per atomic
 };
 
 #define HIP_TRY(expr)                                                                       \
@@ -108,53 +117,74 @@ __device__ __forceinline__ int scale_exp(float amax) {
 // ------------------------------------------------------------ tile kernels
 constexpr int kUnroll = 4;
 
-// 16-byte global accesses with the streaming (non-temporal) cache hint:
-// every byte of a task is touched once per task, so it is not kept in cache.
-#ifndef HICCL_STREAMING
-#define HICCL_STREAMING 1
-#endif
+// Data path. Every operand byte is read and written with buffer
+// instructions that carry the streaming (nt) and device-coherent (sc1)
+// cache policy: a tile's stores are visible to any workgroup on any XCD as
+// soon as they complete, and a dependent tile's loads never hit a stale
+// line in a per-XCD L2 or per-CU L1. Retiring a tile then needs only
+// "stores complete" (s_waitcnt) and a counter increment, with no L2-wide
+// writeback or invalidate. The buffer range of each operand is exactly the
+// tile, so the hardware bounds check drops any access outside it.
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ uint4 ld16(const uint4* p) {
-#if HICCL_STREAMING
-  v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(p));
-  return make_uint4(v.x, v.y, v.z, v.w);
-#else
-  return *p;
-#endif
-}
-__device__ __forceinline__ void st16(uint4* p, uint4 x) {
-#if HICCL_STREAMING
-  v4u v = {x.x, x.y, x.z, x.w};
-  __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(p));
-#else
-  *p = x;
-#endif
-}
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kPolicy = 2 | 16;               // nt | sc1
+constexpr int kRsrcWord3 = 0x00020000;        // raw (untyped) buffer, gfx9 family
 
+__device__ __forceinline__ rsrc_t rsrc(uint64_t base, uint64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(base), 0, int(uint32_t(bytes)), kRsrcWord3);
+}
+__device__ __forceinline__ uint4 ld16(rsrc_t r, uint32_t off) {
+  v4u v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kPolicy);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st16(rsrc_t r, uint32_t off, uint4 x) {
+  v4u v = {x.x, x.y, x.z, x.w};
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, kPolicy);
+}
+__device__ __forceinline__ uint32_t ld4(rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kPolicy);
+}
+__device__ __forceinline__ void st4(rsrc_t r, uint32_t off, uint32_t x) {
+  __builtin_amdgcn_raw_buffer_store_b32(x, r, off, 0, kPolicy);
+}
+__device__ __forceinline__ uint32_t ld2(rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, kPolicy);
+}
+__device__ __forceinline__ void st2(rsrc_t r, uint32_t off, uint32_t x) {
+  __builtin_amdgcn_raw_buffer_store_b16(uint16_t(x), r, off, 0, kPolicy);
+}
+__device__ __forceinline__ uint32_t ld1(rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, kPolicy);
+}
+__device__ __forceinline__ void st1(rsrc_t r, uint32_t off, uint32_t x) {
+  __builtin_amdgcn_raw_buffer_store_b8(uint8_t(x), r, off, 0, kPolicy);
+}
+// wait until this wave's loads and stores have completed
+__device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Copy nb bytes (one tile) from s to d.
 template <int BLOCK>
-__device__ __forceinline__ void copy_bytes(const uint8_t* __restrict__ s, uint8_t* __restrict__ d, uint64_t nb) {
-  const int tid = threadIdx.x;
-  if (((uintptr_t(s) | uintptr_t(d)) & 15u) == 0) {
-    const uint4* sv = reinterpret_cast<const uint4*>(s);
-    uint4* dv = reinterpret_cast<uint4*>(d);
-    uint64_t nv = nb >> 4, i = tid;
+__device__ __forceinline__ void copy_bytes(uint64_t s, uint64_t d, uint64_t nb) {
+  const uint32_t tid = threadIdx.x;
+  const rsrc_t rs = rsrc(s, nb), rd = rsrc(d, nb);
+  if (((s | d) & 15u) == 0) {
+    const uint32_t nv = uint32_t(nb >> 4);
+    uint32_t i = tid;
     for (; i + (kUnroll - 1) * BLOCK < nv; i += kUnroll * BLOCK) {
       uint4 r[kUnroll];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) r[u] = ld16(sv + i + u * BLOCK);
+      for (int u = 0; u < kUnroll; ++u) r[u] = ld16(rs, (i + u * BLOCK) * 16u);
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) st16(dv + i + u * BLOCK, r[u]);
+      for (int u = 0; u < kUnroll; ++u) st16(rd, (i + u * BLOCK) * 16u, r[u]);
     }
-    for (; i < nv; i += BLOCK) dv[i] = sv[i];
-    for (uint64_t b = (nv << 4) + tid; b < nb; b += BLOCK) d[b] = s[b];
-  } else if (((uintptr_t(s) | uintptr_t(d)) & 3u) == 0) {
-    const uint32_t* sw = reinterpret_cast<const uint32_t*>(s);
-    uint32_t* dw = reinterpret_cast<uint32_t*>(d);
-    uint64_t nw = nb >> 2;
-    for (uint64_t i = tid; i < nw; i += BLOCK) dw[i] = sw[i];
-    for (uint64_t b = (nw << 2) + tid; b < nb; b += BLOCK) d[b] = s[b];
+    for (; i < nv; i += BLOCK) st16(rd, i * 16u, ld16(rs, i * 16u));
+    for (uint32_t b = (nv << 4) + tid; b < nb; b += BLOCK) st1(rd, b, ld1(rs, b));
+  } else if (((s | d) & 3u) == 0) {
+    const uint32_t nw = uint32_t(nb >> 2);
+    for (uint32_t i = tid; i < nw; i += BLOCK) st4(rd, i * 4u, ld4(rs, i * 4u));
+    for (uint32_t b = (nw << 2) + tid; b < nb; b += BLOCK) st1(rd, b, ld1(rs, b));
   } else {
-    for (uint64_t b = tid; b < nb; b += BLOCK) d[b] = s[b];
+    for (uint32_t b = tid; b < nb; b += BLOCK) st1(rd, b, ld1(rs, b));
   }
 }
 
@@ -183,110 +213,123 @@ __device__ __forceinline__ uint4 op32v(uint4 a, uint4 b) {
                     op32<FLT, OP>(a.w, b.w));
 }
 
-// Fused reduce of K (compile-time, 0 = runtime k) operands, 32-bit lanes.
-// Operands are combined left to right: ((s0 op s1) op s2) ...
+// Fused reduce of K (compile-time; 0 = runtime k) operands over n 32-bit
+// elements starting at element e0. Operands are combined left to right:
+// ((s0 op s1) op s2) ... in float32 / int32, so the result depends only on
+// the schedule, never on timing.
 template <int BLOCK, bool FLT, int OP, int K>
 __device__ __forceinline__ void reduce32(const DevTask* t, int k, uint64_t e0, uint64_t n) {
-  const int tid = threadIdx.x;
+  const uint32_t tid = threadIdx.x;
   const int kk = K ? K : k;
-  uint32_t* d = reinterpret_cast<uint32_t*>(t->dst) + e0;
-  bool vec = (uintptr_t(d) & 15u) == 0;
+  const uint64_t nb = n * 4;
+  const uint64_t d = t->dst + e0 * 4;
+  const rsrc_t rd = rsrc(d, nb);
+  bool vec = (d & 15u) == 0;
   for (int j = 0; j < kk; ++j) vec = vec && ((src_addr(t, j, kk) + e0 * 4) & 15u) == 0;
-  uint64_t nv = vec ? n >> 2 : 0;
+  const uint32_t nv = vec ? uint32_t(n >> 2) : 0;
   if (nv) {
-    uint4* dv = reinterpret_cast<uint4*>(d);
-    uint64_t i = tid;
-    for (; i + (kUnroll - 1) * BLOCK < nv; i += kUnroll * BLOCK) {
-      uint4 acc[kUnroll];
-      const uint4* s0 = reinterpret_cast<const uint4*>(src_addr(t, 0, kk)) + (e0 >> 2);
+    uint32_t i = tid;
+    if (K) {
+      rsrc_t rs[K ? K : 1];
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) acc[u] = ld16(s0 + i + u * BLOCK);
-      if (K) {
+      for (int j = 0; j < (K ? K : 1); ++j) rs[j] = rsrc(src_addr(t, j, kk) + e0 * 4, nb);
+      for (; i + (kUnroll - 1) * BLOCK < nv; i += kUnroll * BLOCK) {
+        uint4 v[K ? K : 1][kUnroll];
 #pragma unroll
-        for (int j = 1; j < (K ? K : 1); ++j) {
-          const uint4* sj = reinterpret_cast<const uint4*>(src_addr(t, j, kk)) + (e0 >> 2);
-          uint4 v[kUnroll];
+        for (int j = 0; j < (K ? K : 1); ++j)
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) v[u] = ld16(sj + i + u * BLOCK);
+          for (int u = 0; u < kUnroll; ++u) v[j][u] = ld16(rs[j], (i + u * BLOCK) * 16u);
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) acc[u] = op32v<FLT, OP>(acc[u], v[u]);
-        }
-      } else {
-        for (int j = 1; j < kk; ++j) {
-          const uint4* sj = reinterpret_cast<const uint4*>(src_addr(t, j, kk)) + (e0 >> 2);
-          uint4 v[kUnroll];
+        for (int u = 0; u < kUnroll; ++u) {
+          uint4 acc = v[0][u];
 #pragma unroll
-          for (int u = 0; u < kUnroll; ++u) v[u] = ld16(sj + i + u * BLOCK);
-#pragma unroll
-          for (int u = 0; u < kUnroll; ++u) acc[u] = op32v<FLT, OP>(acc[u], v[u]);
+          for (int j = 1; j < (K ? K : 1); ++j) acc = op32v<FLT, OP>(acc, v[j][u]);
+          st16(rd, (i + u * BLOCK) * 16u, acc);
         }
       }
+    } else {
+      for (; i + (kUnroll - 1) * BLOCK < nv; i += kUnroll * BLOCK) {
+        uint4 acc[kUnroll];
+        const rsrc_t r0 = rsrc(src_addr(t, 0, kk) + e0 * 4, nb);
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) st16(dv + i + u * BLOCK, acc[u]);
+        for (int u = 0; u < kUnroll; ++u) acc[u] = ld16(r0, (i + u * BLOCK) * 16u);
+        for (int j = 1; j < kk; ++j) {
+          const rsrc_t rj = rsrc(src_addr(t, j, kk) + e0 * 4, nb);
+          uint4 v[kUnroll];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) v[u] = ld16(rj, (i + u * BLOCK) * 16u);
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) acc[u] = op32v<FLT, OP>(acc[u], v[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) st16(rd, (i + u * BLOCK) * 16u, acc[u]);
+      }
     }
     for (; i < nv; i += BLOCK) {
-      uint4 acc = reinterpret_cast<const uint4*>(src_addr(t, 0, kk))[(e0 >> 2) + i];
-      for (int j = 1; j < kk; ++j)
-        acc = op32v<FLT, OP>(acc, reinterpret_cast<const uint4*>(src_addr(t, j, kk))[(e0 >> 2) + i]);
-      dv[i] = acc;
+      uint4 acc = ld16(rsrc(src_addr(t, 0, kk) + e0 * 4, nb), i * 16u);
+      for (int j = 1; j < kk; ++j) acc = op32v<FLT, OP>(acc, ld16(rsrc(src_addr(t, j, kk) + e0 * 4, nb), i * 16u));
+      st16(rd, i * 16u, acc);
     }
   }
-  for (uint64_t e = (nv << 2) + tid; e < n; e += BLOCK) {
-    uint32_t acc = reinterpret_cast<const uint32_t*>(src_addr(t, 0, kk))[e0 + e];
-    for (int j = 1; j < kk; ++j) acc = op32<FLT, OP>(acc, reinterpret_cast<const uint32_t*>(src_addr(t, j, kk))[e0 + e]);
-    d[e] = acc;
+  for (uint32_t e = (nv << 2) + tid; e < n; e += BLOCK) {
+    uint32_t acc = ld4(rsrc(src_addr(t, 0, kk) + e0 * 4, nb), e * 4u);
+    for (int j = 1; j < kk; ++j) acc = op32<FLT, OP>(acc, ld4(rsrc(src_addr(t, j, kk) + e0 * 4, nb), e * 4u));
+    st4(rd, e * 4u, acc);
   }
 }
 
 // bf16 payload: widen to float32, sum left to right, narrow (RNE).
 template <int BLOCK>
 __device__ __forceinline__ void reduce_bf16(const DevTask* t, int k, uint64_t e0, uint64_t n) {
-  const int tid = threadIdx.x;
-  uint16_t* d = reinterpret_cast<uint16_t*>(t->dst) + e0;
-  bool vec = (uintptr_t(d) & 15u) == 0;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t nb = n * 2;
+  const uint64_t d = t->dst + e0 * 2;
+  const rsrc_t rd = rsrc(d, nb);
+  bool vec = (d & 15u) == 0;
   for (int j = 0; j < k; ++j) vec = vec && ((src_addr(t, j, k) + e0 * 2) & 15u) == 0;
-  uint64_t nv = vec ? n >> 3 : 0;
-  for (uint64_t i = tid; i < nv; i += BLOCK) {
+  const uint32_t nv = vec ? uint32_t(n >> 3) : 0;
+  for (uint32_t i = tid; i < nv; i += BLOCK) {
     float a[8];
     for (int j = 0; j < k; ++j) {
-      uint4 w = ld16(reinterpret_cast<const uint4*>(src_addr(t, j, k)) + (e0 >> 3) + i);
+      uint4 w = ld16(rsrc(src_addr(t, j, k) + e0 * 2, nb), i * 16u);
       float v[8] = {bf16lo(w.x), bf16hi(w.x), bf16lo(w.y), bf16hi(w.y), bf16lo(w.z), bf16hi(w.z), bf16lo(w.w), bf16hi(w.w)};
 #pragma unroll
       for (int q = 0; q < 8; ++q) a[q] = j == 0 ? v[q] : a[q] + v[q];
     }
-    uint4 o = make_uint4(pack_bf16(a[0], a[1]), pack_bf16(a[2], a[3]), pack_bf16(a[4], a[5]), pack_bf16(a[6], a[7]));
-    st16(reinterpret_cast<uint4*>(d) + i, o);
+    st16(rd, i * 16u,
+         make_uint4(pack_bf16(a[0], a[1]), pack_bf16(a[2], a[3]), pack_bf16(a[4], a[5]), pack_bf16(a[6], a[7])));
   }
-  for (uint64_t e = (nv << 3) + tid; e < n; e += BLOCK) {
+  for (uint32_t e = (nv << 3) + tid; e < n; e += BLOCK) {
     float a = 0.f;
     for (int j = 0; j < k; ++j) {
-      float v = __uint_as_float(uint32_t(reinterpret_cast<const uint16_t*>(src_addr(t, j, k))[e0 + e]) << 16);
+      float v = __uint_as_float(ld2(rsrc(src_addr(t, j, k) + e0 * 2, nb), e * 2u) << 16);
       a = j == 0 ? v : a + v;
     }
-    d[e] = uint16_t(to_bf16(a));
+    st2(rd, e * 2u, to_bf16(a));
   }
 }
 
 // fp8 payload with one power-of-two scale per 256 elements. Each lane owns
 // 16 consecutive codes; the 16 lanes of a block find its amax with
 // cross-lane exchanges, pick the new scale, and lane 0 of the group stores
-// it. Counts and offsets are whole blocks, so a group is never split.
+// it. Counts and offsets are whole blocks, so a group is never split, and
+// every lane runs the same number of iterations.
 template <int BLOCK>
 __device__ __forceinline__ void reduce_fp8(const DevTask* t, int k, uint64_t e0, uint64_t n) {
-  const int tid = threadIdx.x;
-  uint8_t* d = reinterpret_cast<uint8_t*>(t->dst) + e0;
-  float* dsc = reinterpret_cast<float*>(t->dst_sc) + e0 / 256;
-  uint64_t nv = n >> 4;                     // 16-code vectors; blocks are whole
-  uint64_t nv_round = (nv + BLOCK - 1) / BLOCK * BLOCK;
-  for (uint64_t i = tid; i < nv_round; i += BLOCK) {
-    bool live = i < nv;
+  const uint32_t tid = threadIdx.x;
+  const rsrc_t rd = rsrc(t->dst + e0, n);
+  const rsrc_t rdsc = rsrc(t->dst_sc + (e0 / 256) * 4, (n / 256) * 4);
+  const uint32_t nv = uint32_t(n >> 4);          // 16-code vectors
+  const uint32_t nv_round = (nv + BLOCK - 1) / BLOCK * BLOCK;
+  for (uint32_t i = tid; i < nv_round; i += BLOCK) {
+    const bool live = i < nv;
     float a[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) a[q] = 0.f;
     if (live) {
       for (int j = 0; j < k; ++j) {
-        uint4 w = ld16(reinterpret_cast<const uint4*>(src_addr(t, j, k) + e0) + i);
-        float sc = reinterpret_cast<const float*>(src_sc_addr(t, j, k))[e0 / 256 + (i >> 4)];
+        uint4 w = ld16(rsrc(src_addr(t, j, k) + e0, n), i * 16u);
+        float sc = __uint_as_float(ld4(rsrc(src_sc_addr(t, j, k) + (e0 / 256) * 4, (n / 256) * 4), (i >> 4) * 4u));
         uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
@@ -300,13 +343,13 @@ __device__ __forceinline__ void reduce_fp8(const DevTask* t, int k, uint64_t e0,
     for (int q = 0; q < 16; ++q) amax = fmaxf(amax, fabsf(a[q]));
 #pragma unroll
     for (int off = 1; off < 16; off <<= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 16));
-    int e = scale_exp(amax);
+    const int e = scale_exp(amax);
     if (live) {
       uint32_t o[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int q = 0; q < 16; ++q) o[q >> 2] |= enc_e4m3(ldexpf(a[q], -e)) << ((q & 3) * 8);
-      st16(reinterpret_cast<uint4*>(d) + i, make_uint4(o[0], o[1], o[2], o[3]));
-      if ((i & 15u) == 0) dsc[i >> 4] = amax == 0.f ? 1.f : ldexpf(1.f, e);
+      st16(rd, i * 16u, make_uint4(o[0], o[1], o[2], o[3]));
+      if ((i & 15u) == 0) st4(rdsc, (i >> 4) * 4u, __float_as_uint(amax == 0.f ? 1.f : ldexpf(1.f, e)));
     }
   }
 }
@@ -320,13 +363,8 @@ __device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t
   const uint64_t n = e1 - e0;
   if (kind == kCopy) {
     const uint64_t es = dt == HICCL_BFLOAT16 ? 2 : (dt == HICCL_FP8_E4M3 ? 1 : 4);
-    copy_bytes<BLOCK>(reinterpret_cast<const uint8_t*>(t->src[0]) + e0 * es, reinterpret_cast<uint8_t*>(t->dst) + e0 * es,
-                      n * es);
-    if (dt == HICCL_FP8_E4M3) {
-      const float* ss = reinterpret_cast<const float*>(t->src_sc[0]) + e0 / 256;
-      float* ds = reinterpret_cast<float*>(t->dst_sc) + e0 / 256;
-      for (uint64_t b = threadIdx.x; b < n / 256; b += BLOCK) ds[b] = ss[b];
-    }
+    copy_bytes<BLOCK>(t->src[0] + e0 * es, t->dst + e0 * es, n * es);
+    if (dt == HICCL_FP8_E4M3) copy_bytes<BLOCK>(t->src_sc[0] + (e0 / 256) * 4, t->dst_sc + (e0 / 256) * 4, (n / 256) * 4);
     return;
   }
   if (dt == HICCL_FLOAT32) {
@@ -367,11 +405,11 @@ __device__ __forceinline__ unsigned long long dev_clock() { return wall_clock64(
 // task's successors and, when it is its collective's last task, stamps the
 // completion time. Called by one thread after the workgroup barrier.
 __device__ __forceinline__ void retire(const ExecArgs& a, const DevTask* t, uint32_t k) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // publish this workgroup's stores device-wide
+  // The tile's data stores are device-coherent and complete (every wave
+  // waited before the workgroup barrier), so counting it is the release.
   uint32_t old = __hip_atomic_fetch_add(&a.done[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (old + 1 != t->ntiles) return;
-  // last tile of the task: take in the other tiles' releases, then release the successors
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+  // last tile of the task: every tile's stores completed before its count, so release the successors
   const uint32_t b = t->succ_begin, e = b + t->nsucc;
   for (uint32_t s = b; s < e; ++s)
     __hip_atomic_fetch_add(&a.pending[a.succ[s]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -383,69 +421,104 @@ __device__ __forceinline__ void retire(const ExecArgs& a, const DevTask* t, uint
 
 // Persistent executor: workgroups claim tiles in table order (a topological
 // order), wait until the tile's task has all predecessors retired, run
-// it, and retire it. Claiming in topological order guarantees progress: a
-// waiting tile only depends on tiles claimed earlier by running workgroups.
-// The wait is bounded; on expiry the run is aborted and every workgroup
-// exits. The last workgroup to leave resets the counters for the next run.
+// it, and retire it. The table is dealt round-robin into `queues` queues
+// (tile t to queue t % queues), each claimed `batch` tiles per atomic by
+// its own pool of workgroups (block b serves queue b % queues) and, once
+// empty, by any workgroup that runs out of work. Every queue is in
+// topological order and a workgroup runs its batch in order, so the
+// earliest unfinished tile is always runnable or claimable: the run makes
+// progress while the grid is resident (one queue makes it independent of
+// residency). The wait is bounded; on expiry the run is aborted and every
+// workgroup exits. The last workgroup to leave resets the counters.
+//
+// Loop shape: thread 0's bookkeeping (retire the tile of the previous
+// iteration, claim the next one, wait for it) is ONE region at the top of
+// the iteration, and the iteration ends with a barrier. Two thread-0
+// regions on either side of the back-edge would let the compiler fuse them
+// into one divergent region around the barriers, which parks lane 0 while
+// the other lanes keep looping.
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void hiccl_persistent(ExecArgs a) {
   __shared__ uint32_t s_tile, s_flag;
   const int tid = threadIdx.x;
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  uint32_t prev = kNone;            // task of the tile this workgroup ran last (uniform)
+  // thread 0's claim state: positions [pos, end) of queue q are this workgroup's
+  const uint32_t Q = a.queues;
+  const uint32_t home = blockIdx.x % Q;
+  uint32_t q = home, pos = 0, end = 0, tried = 0;
   for (;;) {
     if (tid == 0) {
-      uint32_t tl = __hip_atomic_fetch_add(&a.ctl[CTL_CLAIM], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (prev != kNone) retire(a, a.tasks + prev, prev);
+      uint32_t tl = a.ntiles;
+      while (pos >= end && tried < Q) {
+        const uint32_t qlen = (a.ntiles + Q - 1 - q) / Q;
+        uint32_t* ctr = &a.ctl[q * kLine];
+        uint32_t base = qlen;
+        if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < qlen)
+          base = __hip_atomic_fetch_add(ctr, a.batch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (base < qlen) {
+          pos = base;
+          end = min(base + a.batch, qlen);
+        } else {
+          q = (q + 1 == Q) ? 0 : q + 1;    // this queue is drained: help the next one
+          ++tried;
+        }
+      }
+      if (pos < end) tl = (pos++) * Q + q;
       uint32_t flag = 0;
       if (tl == 0 && a.times) a.times[a.ncomm] = dev_clock();
       if (tl < a.ntiles) {
         uint32_t k = a.tile_task[tl];
         uint32_t need = a.tasks[k].npred;
         uint32_t polls = 0;
-        // poll with relaxed device-coherent loads; one acquire fence once the wait is over
-        while (need && __hip_atomic_load(&a.pending[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-          if (__hip_atomic_load(&a.ctl[CTL_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            flag = 1;
-            break;
+        // poll with relaxed device-coherent loads; the tile's data loads are device-coherent too
+        if (need && __hip_atomic_load(&a.pending[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+          while (__hip_atomic_load(&a.pending[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            if (__hip_atomic_load(&a.ctl[CTL_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+              flag = 1;
+              break;
+            }
+            if (++polls >= a.spin_limit) {
+              __hip_atomic_store(&a.ctl[CTL_ABORT], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              __hip_atomic_store(&a.ctl[CTL_STATUS], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              flag = 1;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(2);
           }
-          if (++polls >= a.spin_limit) {
-            __hip_atomic_store(&a.ctl[CTL_ABORT], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&a.ctl[CTL_STATUS], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            flag = 1;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(2);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       s_tile = tl;
       s_flag = flag;
     }
     __syncthreads();
-    const uint32_t tl = s_tile;
-    if (tl >= a.ntiles || s_flag) break;
+    const uint32_t tl = __builtin_amdgcn_readfirstlane(s_tile);
+    const uint32_t flag = __builtin_amdgcn_readfirstlane(s_flag);
+    if (tl >= a.ntiles || flag) break;
     const uint32_t k = __builtin_amdgcn_readfirstlane(a.tile_task[tl]);
-    const DevTask* t = a.tasks + k;
-    run_tile<BLOCK>(t, tl);
-    __syncthreads();
-    if (tid == 0) retire(a, t, k);
+    run_tile<BLOCK>(a.tasks + k, tl);
+    prev = k;
+    wait_mem();        // this wave's stores of the tile have completed ...
+    __syncthreads();   // ... before thread 0 counts the tile in the next iteration
   }
-  __syncthreads();   // every wave has read s_tile / s_flag before they are reused below
+  __syncthreads();     // every wave has read s_tile / s_flag before they are reused below
   if (tid == 0) {
     uint32_t old = __hip_atomic_fetch_add(&a.ctl[CTL_EXIT], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     s_flag = (old + 1 == gridDim.x) ? 2u : 0u;
   }
   __syncthreads();
-  if (s_flag == 2u) {
+  if (__builtin_amdgcn_readfirstlane(s_flag) == 2u) {
+    // last workgroup out: every other workgroup has finished, reset for the next run
     for (uint32_t i = tid; i < a.ntasks; i += BLOCK) {
       a.pending[i] = 0;
       a.done[i] = 0;
     }
     for (uint32_t i = tid; i < a.ncomm; i += BLOCK) a.comm_left[i] = a.comm_ntasks[i];
-    __syncthreads();
+    if (tid < kMaxQueues) a.ctl[tid * kLine] = 0;
     if (tid == 0) {
-      a.ctl[CTL_CLAIM] = 0;
       a.ctl[CTL_ABORT] = 0;
       a.ctl[CTL_EXIT] = 0;
-      __threadfence();
     }
   }
 }
@@ -478,6 +551,8 @@ struct Exe {
   int mode = HICCL_EXEC_PERSISTENT;
   int grid = 0;
   uint32_t spin_limit = 1u << 22;
+  uint32_t queues = kMaxQueues;
+  uint32_t batch = HICCL_CLAIM_BATCH;
 
   ExecArgs args() const {
     ExecArgs a;
@@ -494,6 +569,8 @@ struct Exe {
     a.ntasks = ntasks;
     a.ncomm = ncomm;
     a.spin_limit = spin_limit;
+    a.queues = queues;
+    a.batch = batch;
     return a;
   }
   void free_all() {
@@ -548,7 +625,8 @@ static int device_grid(int want) {
 
 // Flatten plans into one device task table. ws_base[i] is plan i's workspace.
 static int upload(const std::vector<const Plan*>& plans, const std::vector<uint64_t>& ws_base, int mode, int grid,
-                  uint32_t spin_limit, bool with_times, Exe& ex) {
+                  uint32_t spin_limit, bool with_times, Exe& ex, int queues = kMaxQueues,
+                  int batch = HICCL_CLAIM_BATCH) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   ex.device = dev;
@@ -646,6 +724,8 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
     HIP_TRY(hipMemset(ex.d_times, 0, (plans.size() + 1) * sizeof(unsigned long long)));
   }
   ex.grid = std::min<int>(device_grid(grid), std::max<uint32_t>(1u, ex.ntiles));
+  ex.queues = uint32_t(std::max(1, std::min<int>(queues, std::min<int>(kMaxQueues, ex.grid))));
+  ex.batch = uint32_t(std::max(1, batch));
   return 0;
 }
 
@@ -697,7 +777,8 @@ static int ensure_device(Comm& c) {
     }
     ws = uint64_t(reinterpret_cast<uintptr_t>(s->ws));
   }
-  int rc = upload({&c.plan}, {ws}, c.exec.mode, c.exec.grid, c.exec.spin_limit, false, s->exe);
+  int rc = upload({&c.plan}, {ws}, c.exec.mode, c.exec.grid, c.exec.spin_limit, false, s->exe, c.exec.queues,
+                  c.exec.batch);
   if (!rc && hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) != hipSuccess)
     rc = fail(HICCL_ERR_HIP, "event creation failed");
   if (rc) {
@@ -767,12 +848,14 @@ static int batch_prepare(hiccl_batch_s* b) {
   }
   const ExecCfg& x = b->comms[0]->c.exec;
   if (b->mode == HICCL_BATCH_PERSISTENT) {
-    if (int rc = upload(plans, wsb, HICCL_EXEC_PERSISTENT, x.grid, x.spin_limit, true, b->merged)) return rc;
+    if (int rc = upload(plans, wsb, HICCL_EXEC_PERSISTENT, x.grid, x.spin_limit, true, b->merged, x.queues, x.batch))
+      return rc;
   } else {
     b->each.resize(plans.size());
     for (size_t i = 0; i < plans.size(); ++i) {
       const ExecCfg& xi = b->comms[i]->c.exec;
-      if (int rc = upload({plans[i]}, {wsb[i]}, xi.mode, xi.grid, xi.spin_limit, true, b->each[i])) return rc;
+      if (int rc = upload({plans[i]}, {wsb[i]}, xi.mode, xi.grid, xi.spin_limit, true, b->each[i], xi.queues, xi.batch))
+        return rc;
     }
   }
   int dev = 0, khz = 0;

@@ -112,6 +112,8 @@ struct ExecCfg {
   int grid = 0;
   int order = HICCL_ORDER_STAGE;
   uint32_t spin_limit = 1u << 22;
+  int queues = 8;
+  int batch = 4;
 };
 
 struct DeviceState;              // device.hip

@@ -927,10 +927,27 @@ int hiccl_set_exec(hiccl_comm_t comm, int mode, size_t tile_bytes, int grid, int
   return HICCL_SUCCESS;
 }
 
+int hiccl_set_claim(hiccl_comm_t comm, int queues, int batch) {
+  CHECK_COMM(comm);
+  if (queues < 0 || queues > 8 || batch < 0 || batch > 1024)
+    return fail(HICCL_ERR_INVALID_ARG, "queues must be 0..8 and batch 0..1024");
+  comm->c.exec.queues = queues ? queues : 8;
+  comm->c.exec.batch = batch ? batch : 4;
+  if (comm->c.dev) {
+    device_state_free(comm->c.dev);
+    comm->c.dev = nullptr;
+  }
+  return HICCL_SUCCESS;
+}
+
 int hiccl_set_spin_limit(hiccl_comm_t comm, uint32_t polls) {
   CHECK_COMM(comm);
   if (polls == 0) return fail(HICCL_ERR_INVALID_ARG, "spin limit must be >= 1");
   comm->c.exec.spin_limit = polls;
+  if (comm->c.dev) {
+    device_state_free(comm->c.dev);
+    comm->c.dev = nullptr;
+  }
   return HICCL_SUCCESS;
 }
 

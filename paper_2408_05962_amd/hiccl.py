@@ -11,7 +11,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhiccl.so")
+LIB_PATH = os.environ.get("HICCL_LIB") or os.path.join(HERE, "libhiccl.so")
 
 INT32, FLOAT32, BFLOAT16, FP8_E4M3 = 0, 1, 2, 3
 DTYPES = {"int32": INT32, "float32": FLOAT32, "bfloat16": BFLOAT16, "fp8_e4m3": FP8_E4M3}
@@ -75,6 +75,7 @@ def lib():
             "hiccl_set_pipeline": [vp, i],
             "hiccl_set_exec": [vp, i, sz, i, i],
             "hiccl_set_spin_limit": [vp, C.c_uint32],
+            "hiccl_set_claim": [vp, i, i],
             "hiccl_init": [vp],
             "hiccl_workspace_size": [vp, C.POINTER(sz)],
             "hiccl_set_workspace": [vp, vp, sz],
@@ -201,6 +202,9 @@ class Comm:
     def set_exec(self, mode="persistent", tile_bytes=0, grid=0, order="stage"):
         return check(lib().hiccl_set_exec(self.h, EXEC.get(mode, mode), int(tile_bytes), int(grid),
                                           ORDER.get(order, order)))
+
+    def set_claim(self, queues=0, batch=0):
+        return check(lib().hiccl_set_claim(self.h, int(queues), int(batch)))
 
     def set_spin_limit(self, polls):
         return check(lib().hiccl_set_spin_limit(self.h, int(polls)))
