@@ -25,7 +25,8 @@
 namespace hiccl {
 
 // ------------------------------------------------------------ task table
-// 128-byte descriptor. meta = kind | op << 2 | dtype << 4 | nsrc << 8.
+// 128-byte descriptor. meta = kind | op << 2 | dtype << 4 | nsrc << 8;
+// npred = number of predecessor tasks that must retire before it starts.
 // With more than four operands, src[0] / src_sc[0] point at arrays of
 // operand addresses in device memory.
 struct alignas(16) DevTask {
@@ -401,15 +402,16 @@ __device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t
 
 __device__ __forceinline__ unsigned long long dev_clock() { return wall_clock64(); }
 
-// Retire one tile of task `k`: the last tile to finish releases the
-// task's successors and, when it is its collective's last task, stamps the
-// completion time. Called by one thread after the workgroup barrier.
+// Retire one tile of task `k`: the last tile of the task releases its
+// successors and, when the task is its collective's last, stamps the
+// completion time. The tile's data stores are device-coherent and complete
+// (every worker wave waited before the workgroup barrier that precedes this
+// call), so counting it is the release.
 __device__ __forceinline__ void retire(const ExecArgs& a, const DevTask* t, uint32_t k) {
-  // The tile's data stores are device-coherent and complete (every wave
-  // waited before the workgroup barrier), so counting it is the release.
-  uint32_t old = __hip_atomic_fetch_add(&a.done[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (old + 1 != t->ntiles) return;
-  // last tile of the task: every tile's stores completed before its count, so release the successors
+  if (t->ntiles > 1) {
+    uint32_t old = __hip_atomic_fetch_add(&a.done[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 != t->ntiles) return;
+  }
   const uint32_t b = t->succ_begin, e = b + t->nsucc;
   for (uint32_t s = b; s < e; ++s)
     __hip_atomic_fetch_add(&a.pending[a.succ[s]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -425,98 +427,142 @@ __device__ __forceinline__ void retire(const ExecArgs& a, const DevTask* t, uint
 // (tile t to queue t % queues), each claimed `batch` tiles per atomic by
 // its own pool of workgroups (block b serves queue b % queues) and, once
 // empty, by any workgroup that runs out of work. Every queue is in
-// topological order and a workgroup runs its batch in order, so the
+// topological order and a workgroup runs its tiles in claim order, so the
 // earliest unfinished tile is always runnable or claimable: the run makes
 // progress while the grid is resident (one queue makes it independent of
 // residency). The wait is bounded; on expiry the run is aborted and every
 // workgroup exits. The last workgroup to leave resets the counters.
 //
-// Loop shape: thread 0's bookkeeping (retire the tile of the previous
-// iteration, claim the next one, wait for it) is ONE region at the top of
-// the iteration, and the iteration ends with a barrier. Two thread-0
-// regions on either side of the back-edge would let the compiler fuse them
-// into one divergent region around the barriers, which parks lane 0 while
-// the other lanes keep looping.
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void hiccl_persistent(ExecArgs a) {
-  __shared__ uint32_t s_tile, s_flag;
-  const int tid = threadIdx.x;
-  constexpr uint32_t kNone = 0xFFFFFFFFu;
-  uint32_t prev = kNone;            // task of the tile this workgroup ran last (uniform)
-  // thread 0's claim state: positions [pos, end) of queue q are this workgroup's
+// Each workgroup is BLOCK worker threads plus one scheduler wave. While the
+// workers stream tile i, the scheduler (lane 0) retires tile i-1, claims
+// tile i+1 and posts it in the other of two LDS slots, so claim / retire
+// latency hides behind data movement. The scheduler only posts a tile as
+// ready once its predecessors have retired; if they have not after a few
+// polls it posts the tile as not ready: in the next iteration the workers
+// idle while the scheduler retires tile i (the tile may depend on it) and
+// then waits with the full bounded wait. Role branches use wave-uniform
+// conditions, and the scheduler's work is one region per iteration that
+// ends at the iteration's single barrier.
+constexpr uint32_t kNoTile = 0xFFFFFFFFu;
+constexpr uint32_t kNotReady = 0x80000000u;
+
+struct Claim {                      // scheduler lane state
+  uint32_t q, pos, end, tried;
+};
+
+__device__ __forceinline__ uint32_t claim_next(const ExecArgs& a, Claim& c) {
   const uint32_t Q = a.queues;
-  const uint32_t home = blockIdx.x % Q;
-  uint32_t q = home, pos = 0, end = 0, tried = 0;
-  for (;;) {
-    if (tid == 0) {
-      if (prev != kNone) retire(a, a.tasks + prev, prev);
-      uint32_t tl = a.ntiles;
-      while (pos >= end && tried < Q) {
-        const uint32_t qlen = (a.ntiles + Q - 1 - q) / Q;
-        uint32_t* ctr = &a.ctl[q * kLine];
-        uint32_t base = qlen;
-        if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < qlen)
-          base = __hip_atomic_fetch_add(ctr, a.batch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (base < qlen) {
-          pos = base;
-          end = min(base + a.batch, qlen);
-        } else {
-          q = (q + 1 == Q) ? 0 : q + 1;    // this queue is drained: help the next one
-          ++tried;
-        }
-      }
-      if (pos < end) tl = (pos++) * Q + q;
-      uint32_t flag = 0;
-      if (tl == 0 && a.times) a.times[a.ncomm] = dev_clock();
-      if (tl < a.ntiles) {
-        uint32_t k = a.tile_task[tl];
-        uint32_t need = a.tasks[k].npred;
-        uint32_t polls = 0;
-        // poll with relaxed device-coherent loads; the tile's data loads are device-coherent too
-        if (need && __hip_atomic_load(&a.pending[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-          while (__hip_atomic_load(&a.pending[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-            if (__hip_atomic_load(&a.ctl[CTL_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-              flag = 1;
-              break;
-            }
-            if (++polls >= a.spin_limit) {
-              __hip_atomic_store(&a.ctl[CTL_ABORT], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              __hip_atomic_store(&a.ctl[CTL_STATUS], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              flag = 1;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-          }
-        }
-      }
-      s_tile = tl;
-      s_flag = flag;
+  while (c.pos >= c.end && c.tried < Q) {
+    const uint32_t qlen = (a.ntiles + Q - 1 - c.q) / Q;
+    uint32_t* ctr = &a.ctl[c.q * kLine];
+    uint32_t base = qlen;
+    if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < qlen)
+      base = __hip_atomic_fetch_add(ctr, a.batch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (base < qlen) {
+      c.pos = base;
+      c.end = min(base + a.batch, qlen);
+    } else {
+      c.q = (c.q + 1 == Q) ? 0 : c.q + 1;   // this queue is drained: help the next one
+      ++c.tried;
     }
-    __syncthreads();
-    const uint32_t tl = __builtin_amdgcn_readfirstlane(s_tile);
-    const uint32_t flag = __builtin_amdgcn_readfirstlane(s_flag);
-    if (tl >= a.ntiles || flag) break;
-    const uint32_t k = __builtin_amdgcn_readfirstlane(a.tile_task[tl]);
-    run_tile<BLOCK>(a.tasks + k, tl);
-    prev = k;
-    wait_mem();        // this wave's stores of the tile have completed ...
-    __syncthreads();   // ... before thread 0 counts the tile in the next iteration
   }
-  __syncthreads();     // every wave has read s_tile / s_flag before they are reused below
-  if (tid == 0) {
+  if (c.pos >= c.end) return kNoTile;
+  const uint32_t tl = (c.pos++) * Q + c.q;
+  if (tl == 0 && a.times) a.times[a.ncomm] = dev_clock();
+  return tl;
+}
+
+// Poll task k's predecessor count up to `polls` times; true once all retired.
+__device__ __forceinline__ bool poll_ready(const ExecArgs& a, uint32_t k, uint32_t polls) {
+  const uint32_t need = a.tasks[k].npred;
+  for (uint32_t i = 0; need; ++i) {
+    if (__hip_atomic_load(&a.pending[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
+    if (i + 1 >= polls) return false;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return true;
+}
+
+// Bounded wait for task k's predecessors; false if the run aborts.
+__device__ __forceinline__ bool wait_ready(const ExecArgs& a, uint32_t k) {
+  const uint32_t need = a.tasks[k].npred;
+  if (!need) return true;
+  uint32_t polls = 0;
+  while (__hip_atomic_load(&a.pending[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+    if (__hip_atomic_load(&a.ctl[CTL_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if (++polls >= a.spin_limit) {
+      __hip_atomic_store(&a.ctl[CTL_ABORT], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.ctl[CTL_STATUS], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
+}
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
+  __shared__ uint32_t s_slot[2], s_flag;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x) / 64;   // wave-uniform
+  const bool sched = wave == BLOCK / 64;
+  const bool lead = threadIdx.x == BLOCK;                                  // the scheduler's lane 0
+  Claim c{blockIdx.x % a.queues, 0, 0, 0};
+  if (sched) {
+    if (lead) {
+      // nothing of this workgroup is in flight yet: a full wait cannot block on itself
+      uint32_t tl = claim_next(a, c);
+      if (tl != kNoTile && !wait_ready(a, a.tile_task[tl])) tl = kNoTile;
+      s_slot[0] = tl;
+    }
+  }
+  __syncthreads();
+  uint32_t cur = 0, prev = kNoTile;
+  for (;;) {
+    const uint32_t v = __builtin_amdgcn_readfirstlane(s_slot[cur]);
+    if (v == kNoTile) break;
+    const bool ready = (v & kNotReady) == 0;
+    const uint32_t tl = v & ~kNotReady;
+    if (sched) {
+      if (lead) {
+        if (prev != kNoTile) retire(a, a.tasks + a.tile_task[prev], a.tile_task[prev]);
+        uint32_t post;
+        if (ready) {
+          // the workers run tl now: claim the next tile; it may depend on tl, so do not block on it
+          const uint32_t nx = claim_next(a, c);
+          post = nx == kNoTile ? kNoTile : (poll_ready(a, a.tile_task[nx], 4) ? nx : (nx | kNotReady));
+        } else {
+          // the workers idle this iteration; everything of ours has retired, so wait in full
+          post = wait_ready(a, a.tile_task[tl]) ? tl : kNoTile;
+        }
+        s_slot[cur ^ 1] = post;
+      }
+    } else if (ready) {
+      const uint32_t k = __builtin_amdgcn_readfirstlane(a.tile_task[tl]);
+      run_tile<BLOCK>(a.tasks + k, tl);
+      wait_mem();      // this wave's stores of the tile have completed before the barrier
+    }
+    prev = ready ? tl : kNoTile;
+    cur ^= 1;
+    __syncthreads();
+  }
+  if (sched) {
+    if (lead && prev != kNoTile) retire(a, a.tasks + a.tile_task[prev], a.tile_task[prev]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
     uint32_t old = __hip_atomic_fetch_add(&a.ctl[CTL_EXIT], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     s_flag = (old + 1 == gridDim.x) ? 2u : 0u;
   }
   __syncthreads();
   if (__builtin_amdgcn_readfirstlane(s_flag) == 2u) {
     // last workgroup out: every other workgroup has finished, reset for the next run
-    for (uint32_t i = tid; i < a.ntasks; i += BLOCK) {
+    for (uint32_t i = threadIdx.x; i < a.ntasks; i += BLOCK + 64) {
       a.pending[i] = 0;
       a.done[i] = 0;
     }
-    for (uint32_t i = tid; i < a.ncomm; i += BLOCK) a.comm_left[i] = a.comm_ntasks[i];
-    if (tid < kMaxQueues) a.ctl[tid * kLine] = 0;
-    if (tid == 0) {
+    for (uint32_t i = threadIdx.x; i < a.ncomm; i += BLOCK + 64) a.comm_left[i] = a.comm_ntasks[i];
+    if (threadIdx.x < kMaxQueues) a.ctl[threadIdx.x * kLine] = 0;
+    if (threadIdx.x == 0) {
       a.ctl[CTL_ABORT] = 0;
       a.ctl[CTL_EXIT] = 0;
     }
@@ -616,7 +662,7 @@ static int device_grid(int want) {
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(hiccl_persistent<kBlock>),
-                                                     kBlock, 0) != hipSuccess)
+                                                     kBlock + 64, 0) != hipSuccess)
       per = 4;
     cached = std::max(1, cus * std::max(1, per));
   }
@@ -733,7 +779,7 @@ static int launch(const Exe& ex, hipStream_t st) {
   if (ex.ntiles == 0) return 0;
   ExecArgs a = ex.args();
   if (ex.mode == HICCL_EXEC_PERSISTENT) {
-    hipLaunchKernelGGL(hiccl_persistent<kBlock>, dim3(ex.grid), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL(hiccl_persistent<kBlock>, dim3(ex.grid), dim3(kBlock + 64), 0, st, a);
   } else {
     for (size_t s = 0; s + 1 < ex.stage_tile_begin.size(); ++s) {
       uint32_t lo = ex.stage_tile_begin[s], hi = ex.stage_tile_begin[s + 1];
