@@ -246,7 +246,8 @@ int hiccl_validate_host(hiccl_comm_t comm, uint64_t seed, int norders);
 typedef enum {
   HICCL_BATCH_PERSISTENT = 0,  /* all task tables merged into one persistent launch */
   HICCL_BATCH_GRAPH = 1,       /* one launch per collective, captured once into a hipGraph and replayed */
-  HICCL_BATCH_SERIAL = 2       /* one launch per collective on the stream (reference form) */
+  HICCL_BATCH_SERIAL = 2,      /* one launch per collective on the stream (reference form) */
+  HICCL_BATCH_PERSISTENT_SJF = 3  /* one merged launch, smallest collectives claimed first */
 } hiccl_batch_mode;
 
 /* Group initialized communicators (any mix of dtypes and hierarchies) into

@@ -378,3 +378,109 @@ def sum_f32(ops: list[np.ndarray]) -> np.ndarray:
     for v in ops[1:]:
         acc = (acc + np.asarray(v, dtype=np.float32)).astype(np.float32)
     return acc
+
+
+# ------------------------------------------------------------- hybrid ring + tree
+def ring_depth(h: list[int], n: int) -> int:
+    """Depth k whose groups are the ring's conceptual nodes (p/n ranks each), or raise."""
+    B = block_sizes(h)
+    p = B[0]
+    if n < 1 or p % n:
+        raise ValueError("ring length must divide p")
+    for k in range(len(B)):
+        if B[k] == p // n:
+            return k
+    raise ValueError("p / ring must be a group size of the hierarchy")
+
+
+def ring_chain(root: int, leaves, h: list[int], n: int) -> list[int]:
+    """First ranks of the conceptual nodes the ring visits after the root's, in ring order (Sec. 4.4):
+    the next node, the one after, ... skipping nodes without a leaf."""
+    k = ring_depth(h, n)
+    size = block_sizes(h)[k]
+    mine = root // size
+    out = []
+    for c in range(1, n):
+        node = (mine + c) % n
+        lo = node * size
+        if any(lo <= x < lo + size for x in leaves):
+            out.append(lo)
+    return out
+
+
+def ring_multicast_hops(root: int, leaves, h: list[int], n: int, s: int = 1, align: int = 1, count: int = None):
+    """Hops of a multicast under ring(n) and stripe(s): striping, then the ring, then trees (Sec. 4.4).
+
+    Returns (hops, nstages): each hop carries (src, dst, depth, stage, stripe, ring_step). Stage 0 is the
+    intra-node scatter, ring hops follow one stage per node, and every node's inner tree starts when
+    its holder has the stripe."""
+    leaves = set(leaves)
+    k = ring_depth(h, n)
+    size = block_sizes(h)[k]
+    inner = h[k:]
+    if s > 1:
+        own = stripe_owners(root, [x for x in leaves], h, s)
+    else:
+        own = None
+    if own is None:
+        own = [root]
+    hops = []
+
+    def inner_tree(src, lv, lo, stage, stripe):
+        # the tree inside one conceptual node, on the inner hierarchy
+        loc = [x - lo for x in lv]
+        for hp in multicast_hops(src - lo, loc, inner, stage0=stage, stripe=stripe):
+            hops.append(Hop(hp.src + lo, hp.dst + lo, depth(hp.src + lo, hp.dst + lo, h), hp.stage, stripe))
+
+    chain = ring_chain(root, leaves, h, n)
+    for t, o in enumerate(own):
+        st = 0
+        if o != root:
+            hops.append(Hop(root, o, depth(root, o, h), 0, t))
+            st = 1
+        off = o % size
+        lo0 = (root // size) * size
+        inner_tree(o, [x for x in leaves if lo0 <= x < lo0 + size and x not in (o, root)], lo0, st, t)
+        prev, pst = o, st
+        for c, lo in enumerate(chain):
+            dst = lo + off
+            hops.append(Hop(prev, dst, depth(prev, dst, h), pst, t))
+            inner_tree(dst, [x for x in leaves if lo <= x < lo + size and x != dst], lo, pst + 1, t)
+            prev, pst = dst, pst + 1
+    nst = 1 + max(hp.stage for hp in hops) if hops else 0
+    return hops, nst
+
+
+def ring_reduce(values: dict, leaves, root: int, h: list[int], n: int, combine):
+    """R(leaves, root) under ring(n) without striping: each conceptual node reduces its own leaves by its
+    inner tree; the top node of a node's tree also takes the partial arriving from the next node of the
+    ring, as its last operand; the root's node finishes the sum. ``values[r]`` are leaf operands."""
+    k = ring_depth(h, n)
+    size = block_sizes(h)[k]
+    inner = h[k:]
+    leaves = sorted(set(leaves))
+    chain = ring_chain(root, leaves, h, n)
+    off = root % size
+
+    def node_value(lo, holder, incoming):
+        lv = [x - lo for x in leaves if lo <= x < lo + size]
+        if not lv:
+            return incoming
+        tree = reduction_tree(lv, holder - lo, inner)
+
+        def ev(t, top):
+            if isinstance(t, int):
+                v = values[t + lo]
+                return v if not (top and incoming is not None) else combine([v, incoming])
+            ops = [ev(c, False) for c in t.children]
+            if top and incoming is not None:
+                ops.append(incoming)
+            return combine(ops)
+
+        return ev(tree, True)
+
+    incoming = None
+    for lo in reversed(chain):
+        incoming = node_value(lo, lo + off, incoming)
+    lo0 = (root // size) * size
+    return node_value(lo0, root, incoming)

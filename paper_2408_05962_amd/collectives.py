@@ -87,12 +87,13 @@ def compose(comm: Comm, name: str, send, recv, d: int, root: int = 0, op: str = 
 
 def make(name: str, p: int, dtype, send, recv, d: int, hierarchy=None, stripe: int = 1, pipeline: int = 1,
          root: int = 0, op: str = "sum", form: str = "listing", exec_mode: str = "persistent", tile_bytes: int = 0,
-         grid: int = 0, order: str = "stage", init: bool = True) -> Comm:
+         grid: int = 0, order: str = "stage", init: bool = True, ring: int = 1) -> Comm:
     """Create, compose and (by default) initialize a communicator for one collective."""
     c = Comm(p, dtype)
     compose(c, name, send, recv, d, root=root, op=op, form=form)
     c.set_hierarchy(hierarchy or [p])
     c.set_stripe(stripe)
+    c.set_ring(ring)
     c.set_pipeline(pipeline)
     c.set_exec(exec_mode, tile_bytes, grid, order)
     if init:

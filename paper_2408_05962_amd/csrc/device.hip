@@ -355,7 +355,10 @@ __device__ __forceinline__ void reduce_fp8(const DevTask* t, int k, uint64_t e0,
   }
 }
 
-template <int BLOCK>
+// NARROW = the table may hold bf16 / fp8 tasks; without it those paths are
+// compiled out, which keeps the register budget (and occupancy) of the
+// int32 / float32 executor higher.
+template <int BLOCK, bool NARROW>
 __device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t tile) {
   const uint32_t meta = t->meta;
   const int kind = meta & 3, op = (meta >> 2) & 3, dt = (meta >> 4) & 15, k = int(meta >> 8);
@@ -365,7 +368,8 @@ __device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t
   if (kind == kCopy) {
     const uint64_t es = dt == HICCL_BFLOAT16 ? 2 : (dt == HICCL_FP8_E4M3 ? 1 : 4);
     copy_bytes<BLOCK>(t->src[0] + e0 * es, t->dst + e0 * es, n * es);
-    if (dt == HICCL_FP8_E4M3) copy_bytes<BLOCK>(t->src_sc[0] + (e0 / 256) * 4, t->dst_sc + (e0 / 256) * 4, (n / 256) * 4);
+    if (NARROW && dt == HICCL_FP8_E4M3)
+      copy_bytes<BLOCK>(t->src_sc[0] + (e0 / 256) * 4, t->dst_sc + (e0 / 256) * 4, (n / 256) * 4);
     return;
   }
   if (dt == HICCL_FLOAT32) {
@@ -393,9 +397,9 @@ __device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t
     } else {
       reduce32<BLOCK, false, HICCL_MIN, 0>(t, k, e0, n);
     }
-  } else if (dt == HICCL_BFLOAT16) {
+  } else if (NARROW && dt == HICCL_BFLOAT16) {
     reduce_bf16<BLOCK>(t, k, e0, n);
-  } else {
+  } else if (NARROW) {
     reduce_fp8<BLOCK>(t, k, e0, n);
   }
 }
@@ -500,7 +504,7 @@ __device__ __forceinline__ bool wait_ready(const ExecArgs& a, uint32_t k) {
   return true;
 }
 
-template <int BLOCK>
+template <int BLOCK, bool NARROW>
 __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
   __shared__ uint32_t s_slot[2], s_flag;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x) / 64;   // wave-uniform
@@ -538,7 +542,7 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
       }
     } else if (ready) {
       const uint32_t k = __builtin_amdgcn_readfirstlane(a.tile_task[tl]);
-      run_tile<BLOCK>(a.tasks + k, tl);
+      run_tile<BLOCK, NARROW>(a.tasks + k, tl);
       wait_mem();      // this wave's stores of the tile have completed before the barrier
     }
     prev = ready ? tl : kNoTile;
@@ -571,11 +575,11 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
 
 // One launch per dependency stage: the kernel boundary orders the stages,
 // so no counters are used.
-template <int BLOCK>
+template <int BLOCK, bool NARROW>
 __global__ __launch_bounds__(BLOCK) void hiccl_staged(ExecArgs a, uint32_t lo, uint32_t hi) {
   for (uint32_t tl = lo + blockIdx.x; tl < hi; tl += gridDim.x) {
     const uint32_t k = __builtin_amdgcn_readfirstlane(a.tile_task[tl]);
-    run_tile<BLOCK>(a.tasks + k, tl);
+    run_tile<BLOCK, NARROW>(a.tasks + k, tl);
   }
 }
 
@@ -599,6 +603,7 @@ struct Exe {
   uint32_t spin_limit = 1u << 22;
   uint32_t queues = kMaxQueues;
   uint32_t batch = HICCL_CLAIM_BATCH;
+  bool narrow = false;             // some task carries a bf16 / fp8 payload
 
   ExecArgs args() const {
     ExecArgs a;
@@ -655,24 +660,27 @@ void device_state_free(DeviceState* s) {
   delete s;
 }
 
-static int device_grid(int want) {
-  static int cached = 0;
-  if (!cached) {
+static int device_grid(int want, bool narrow) {
+  static int cached[2] = {0, 0};
+  int& c = cached[narrow ? 1 : 0];
+  if (!c) {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(hiccl_persistent<kBlock>),
-                                                     kBlock + 64, 0) != hipSuccess)
-      per = 4;
-    cached = std::max(1, cus * std::max(1, per));
+    const void* k = narrow ? reinterpret_cast<const void*>(hiccl_persistent<kBlock, true>)
+                           : reinterpret_cast<const void*>(hiccl_persistent<kBlock, false>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kBlock + 64, 0) != hipSuccess) per = 3;
+    c = std::max(1, cus * std::max(1, per));
   }
-  return want > 0 ? want : cached;
+  return want > 0 ? want : c;
 }
 
 // Flatten plans into one device task table. ws_base[i] is plan i's workspace.
+// merge: 0 = interleave the collectives by dependency stage; 1 = smallest
+// collective first (by executed bytes), each in stage order.
 static int upload(const std::vector<const Plan*>& plans, const std::vector<uint64_t>& ws_base, int mode, int grid,
                   uint32_t spin_limit, bool with_times, Exe& ex, int queues = kMaxQueues,
-                  int batch = HICCL_CLAIM_BATCH) {
+                  int batch = HICCL_CLAIM_BATCH, int merge = 0) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   ex.device = dev;
@@ -686,10 +694,19 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
   std::vector<Ref> refs;
   for (uint32_t p = 0; p < plans.size(); ++p)
     for (uint32_t i = 0; i < plans[p]->tasks.size(); ++i) refs.push_back({p, i});
-  if (plans.size() > 1)
+  if (plans.size() > 1 && merge == 0) {
     std::stable_sort(refs.begin(), refs.end(), [&](const Ref& x, const Ref& y) {
       return plans[x.plan]->tasks[x.idx].stage < plans[y.plan]->tasks[y.idx].stage;
     });
+  } else if (plans.size() > 1) {
+    std::vector<uint64_t> bytes(plans.size());
+    for (size_t q = 0; q < plans.size(); ++q) bytes[q] = plans[q]->hbm_read + plans[q]->hbm_written;
+    std::stable_sort(refs.begin(), refs.end(), [&](const Ref& x, const Ref& y) {
+      if (bytes[x.plan] != bytes[y.plan]) return bytes[x.plan] < bytes[y.plan];
+      if (x.plan != y.plan) return x.plan < y.plan;
+      return plans[x.plan]->tasks[x.idx].stage < plans[y.plan]->tasks[y.idx].stage;
+    });
+  }
   std::vector<std::vector<uint32_t>> newidx(plans.size());
   for (uint32_t p = 0; p < plans.size(); ++p) newidx[p].resize(plans[p]->tasks.size());
   for (uint32_t i = 0; i < refs.size(); ++i) newidx[refs[i].plan][refs[i].idx] = i;
@@ -733,6 +750,7 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
     for (uint32_t q = 0; q < t.ntiles; ++q) tile_task.push_back(uint32_t(i));
     comm_n[refs[i].plan] += 1;
     nstages = std::max(nstages, t.stage + 1);
+    if (t.dtype == HICCL_BFLOAT16 || t.dtype == HICCL_FP8_E4M3) ex.narrow = true;
   }
   ex.ntasks = uint32_t(nt);
   ex.ntiles = uint32_t(tile_task.size());
@@ -769,7 +787,7 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
     HIP_TRY(hipMalloc(reinterpret_cast<void**>(&ex.d_times), (plans.size() + 1) * sizeof(unsigned long long)));
     HIP_TRY(hipMemset(ex.d_times, 0, (plans.size() + 1) * sizeof(unsigned long long)));
   }
-  ex.grid = std::min<int>(device_grid(grid), std::max<uint32_t>(1u, ex.ntiles));
+  ex.grid = std::min<int>(device_grid(grid, ex.narrow), std::max<uint32_t>(1u, ex.ntiles));
   ex.queues = uint32_t(std::max(1, std::min<int>(queues, std::min<int>(kMaxQueues, ex.grid))));
   ex.batch = uint32_t(std::max(1, batch));
   return 0;
@@ -779,13 +797,19 @@ static int launch(const Exe& ex, hipStream_t st) {
   if (ex.ntiles == 0) return 0;
   ExecArgs a = ex.args();
   if (ex.mode == HICCL_EXEC_PERSISTENT) {
-    hipLaunchKernelGGL(hiccl_persistent<kBlock>, dim3(ex.grid), dim3(kBlock + 64), 0, st, a);
+    if (ex.narrow)
+      hipLaunchKernelGGL((hiccl_persistent<kBlock, true>), dim3(ex.grid), dim3(kBlock + 64), 0, st, a);
+    else
+      hipLaunchKernelGGL((hiccl_persistent<kBlock, false>), dim3(ex.grid), dim3(kBlock + 64), 0, st, a);
   } else {
     for (size_t s = 0; s + 1 < ex.stage_tile_begin.size(); ++s) {
       uint32_t lo = ex.stage_tile_begin[s], hi = ex.stage_tile_begin[s + 1];
       if (hi <= lo) continue;
-      int g = int(std::min<uint32_t>(hi - lo, uint32_t(device_grid(0) * 2)));
-      hipLaunchKernelGGL(hiccl_staged<kBlock>, dim3(g), dim3(kBlock), 0, st, a, lo, hi);
+      int g = int(std::min<uint32_t>(hi - lo, uint32_t(device_grid(0, ex.narrow) * 2)));
+      if (ex.narrow)
+        hipLaunchKernelGGL((hiccl_staged<kBlock, true>), dim3(g), dim3(kBlock), 0, st, a, lo, hi);
+      else
+        hipLaunchKernelGGL((hiccl_staged<kBlock, false>), dim3(g), dim3(kBlock), 0, st, a, lo, hi);
     }
   }
   HIP_TRY(hipGetLastError());
@@ -893,8 +917,9 @@ static int batch_prepare(hiccl_batch_s* b) {
     wsb.push_back(uint64_t(reinterpret_cast<uintptr_t>(c->c.dev->ws)));
   }
   const ExecCfg& x = b->comms[0]->c.exec;
-  if (b->mode == HICCL_BATCH_PERSISTENT) {
-    if (int rc = upload(plans, wsb, HICCL_EXEC_PERSISTENT, x.grid, x.spin_limit, true, b->merged, x.queues, x.batch))
+  if (b->mode == HICCL_BATCH_PERSISTENT || b->mode == HICCL_BATCH_PERSISTENT_SJF) {
+    if (int rc = upload(plans, wsb, HICCL_EXEC_PERSISTENT, x.grid, x.spin_limit, true, b->merged, x.queues, x.batch,
+                        b->mode == HICCL_BATCH_PERSISTENT_SJF ? 1 : 0))
       return rc;
   } else {
     b->each.resize(plans.size());
@@ -917,7 +942,8 @@ extern "C" {
 
 int hiccl_batch_create(const hiccl_comm_t* comms, int n, int mode, hiccl_batch_t* out) {
   if (!comms || n < 1 || !out) return fail(HICCL_ERR_INVALID_ARG, "batch needs at least one communicator");
-  if (mode < HICCL_BATCH_PERSISTENT || mode > HICCL_BATCH_SERIAL) return fail(HICCL_ERR_INVALID_ARG, "bad batch mode");
+  if (mode < HICCL_BATCH_PERSISTENT || mode > HICCL_BATCH_PERSISTENT_SJF)
+    return fail(HICCL_ERR_INVALID_ARG, "bad batch mode");
   for (int i = 0; i < n; ++i) {
     if (!comms[i]) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator in batch");
     if (!comms[i]->c.planned) return fail(HICCL_ERR_STATE, "batch members must be initialized");
@@ -936,7 +962,7 @@ int hiccl_batch_create(const hiccl_comm_t* comms, int n, int mode, hiccl_batch_t
 int hiccl_batch_run(hiccl_batch_t b, void* stream) {
   if (!b) return fail(HICCL_ERR_INVALID_ARG, "NULL batch");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (b->mode == HICCL_BATCH_PERSISTENT) {
+  if (b->mode == HICCL_BATCH_PERSISTENT || b->mode == HICCL_BATCH_PERSISTENT_SJF) {
     if (int rc = launch(b->merged, st)) return rc;
   } else if (b->mode == HICCL_BATCH_SERIAL) {
     for (const Exe& e : b->each)
@@ -967,7 +993,7 @@ int hiccl_batch_wait(hiccl_batch_t b) {
   if (!b->launched) return HICCL_SUCCESS;
   HIP_TRY(hipEventSynchronize(b->ev));
   int bad = 0;
-  if (b->mode == HICCL_BATCH_PERSISTENT) {
+  if (b->mode == HICCL_BATCH_PERSISTENT || b->mode == HICCL_BATCH_PERSISTENT_SJF) {
     int s = 0;
     if (int rc = read_status(b->merged, &s)) return rc;
     bad |= s;
@@ -985,7 +1011,7 @@ int hiccl_batch_wait(hiccl_batch_t b) {
 int hiccl_batch_times(hiccl_batch_t b, uint64_t* ns, int n) {
   if (!b || !ns || n != int(b->comms.size())) return fail(HICCL_ERR_INVALID_ARG, "bad batch times request");
   std::vector<unsigned long long> stamp(n), start;
-  if (b->mode == HICCL_BATCH_PERSISTENT) {
+  if (b->mode == HICCL_BATCH_PERSISTENT || b->mode == HICCL_BATCH_PERSISTENT_SJF) {
     std::vector<unsigned long long> t(n + 1);
     HIP_TRY(hipMemcpy(t.data(), b->merged.d_times, (n + 1) * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     for (int i = 0; i < n; ++i) stamp[i] = t[i];

@@ -94,8 +94,38 @@ struct Factorizer {
   uint64_t& ws_top;
   std::vector<Op>& ops;
 
+  int kr = 0;                     // depth whose groups are the ring's conceptual nodes (0: no ring)
+
   Factorizer(const Comm& c_, const Prim& p_, uint64_t& ws, std::vector<Op>& out)
-      : c(c_), p(p_), dt(c_.dtype), B(group_sizes(c_.hier, c_.P)), L(int(c_.hier.size())), ws_top(ws), ops(out) {}
+      : c(c_), p(p_), dt(c_.dtype), B(group_sizes(c_.hier, c_.P)), L(int(c_.hier.size())), ws_top(ws), ops(out) {
+    if (c.ring > 1)
+      for (int k = 1; k <= L; ++k)
+        if (B[k] == c.P / c.ring) kr = k;
+  }
+
+  // First ranks of the conceptual nodes the ring visits after the one of
+  // rank `r`, in ring order (the next node, the one after, ...), skipping
+  // nodes that hold no leaf (Sec. 4.4).
+  std::vector<int> ring_chain(int r, const std::vector<int>& leaves) const {
+    std::vector<int> out;
+    const int size = B[kr], mine = r / size;
+    for (int ci = 1; ci < c.ring; ++ci) {
+      int lo = ((mine + ci) % c.ring) * size;
+      for (int x : leaves)
+        if (x >= lo && x < lo + size) {
+          out.push_back(lo);
+          break;
+        }
+    }
+    return out;
+  }
+
+  static std::vector<int> in_range(const std::vector<int>& v, int lo, int hi, int skip_a = -1, int skip_b = -1) {
+    std::vector<int> o;
+    for (int x : v)
+      if (x >= lo && x < hi && x != skip_a && x != skip_b) o.push_back(x);
+    return o;
+  }
 
   Loc user(const hiccl_buf_t& b, uint64_t off) const {
     Loc l;
@@ -118,8 +148,9 @@ struct Factorizer {
   }
 
   void copy(const Loc& s, int sr, const Loc& d, int dr, bool dws, uint64_t n, uint64_t off, int stripe,
-            bool whole = false) {
+            bool whole = false, int ring_step = 0) {
     Op o;
+    o.ring_step = ring_step;
     o.kind = kCopy;
     o.src = {s};
     o.src_rank = {sr};
@@ -140,7 +171,7 @@ struct Factorizer {
   std::vector<int> owners(const std::vector<int>& leaves) const {
     int s = c.stripe;
     if (s <= 1) return {};
-    for (int k = L; k >= 0; --k) {
+    for (int k = L; k >= kr; --k) {
       int size = B[k];
       if (size >= s && size % s == 0) {
         int lo = p.root / size * size;
@@ -201,6 +232,43 @@ struct Factorizer {
     for (int x : leaves)
       if (x != r) others.push_back(x);
     std::vector<int> own = owners(leaves);
+    if (kr > 0) {
+      // ring + tree (Sec. 4.4): striping, then each stripe runs along a rail through the
+      // conceptual nodes, then a tree inside every node
+      std::vector<std::pair<uint64_t, uint64_t>> pieces =
+          own.empty() ? std::vector<std::pair<uint64_t, uint64_t>>{{0, p.count}}
+                      : split_range(p.count, int(own.size()), align_elems(dt));
+      if (own.empty()) own = {r};
+      const int size = B[kr], lo0 = r / size * size;
+      std::vector<int> chain = ring_chain(r, leaves);
+      for (size_t t = 0; t < own.size(); ++t) {
+        uint64_t off = pieces[t].first, len = pieces[t].second;
+        if (len == 0) continue;
+        int o = own[t];
+        int stripe = own.size() > 1 ? int(t) : 0;
+        Loc ol;
+        if (o == r) {
+          ol = rs.at(off, dt);
+        } else {
+          bool oleaf = std::binary_search(leaves.begin(), leaves.end(), o);
+          ol = oleaf ? user(p.recv[o], off) : ws(len);
+          copy(rs.at(off, dt), r, ol, o, !oleaf, len, off, stripe);
+        }
+        mcast(o, ol, in_range(leaves, lo0, lo0 + size, o, r), lo0, kr + 1, off, len, stripe);
+        int prev = o;
+        Loc pl = ol;
+        for (size_t ci = 0; ci < chain.size(); ++ci) {
+          int dst = chain[ci] + (o - lo0);
+          bool dleaf = std::binary_search(leaves.begin(), leaves.end(), dst);
+          Loc dl = dleaf ? user(p.recv[dst], off) : ws(len);
+          copy(pl, prev, dl, dst, !dleaf, len, off, stripe, false, int(ci) + 1);
+          mcast(dst, dl, in_range(leaves, chain[ci], chain[ci] + size, dst), chain[ci], kr + 1, off, len, stripe);
+          prev = dst;
+          pl = dl;
+        }
+      }
+      return;
+    }
     if (own.empty()) {
       mcast(r, rs, others, 0, 1, 0, p.count, 0);
       return;
@@ -275,9 +343,11 @@ struct Factorizer {
 
   // Emit a node's operands first, then the node. Operands are combined in
   // ascending child-group order. Returns the location of the node value.
-  Loc emit_node(const RNode& nd, uint64_t off, uint64_t n, int stripe, const Loc* final_dst, bool final_ws) {
+  Loc emit_node(const RNode& nd, uint64_t off, uint64_t n, int stripe, const Loc* final_dst, bool final_ws,
+                const Loc* extra = nullptr, int extra_rank = -1, int ring_step = 0) {
     Op o;
     o.kind = kReduce;
+    o.ring_step = ring_step;
     for (const RNode& ch : nd.kids) {
       if (ch.leaf >= 0) {
         o.src.push_back(user(p.send[ch.leaf], off));
@@ -285,6 +355,10 @@ struct Factorizer {
         o.src.push_back(emit_node(ch, off, n, stripe, nullptr, true));
       }
       o.src_rank.push_back(ch.host);
+    }
+    if (extra) {          // the partial arriving from the next node of the ring, last
+      o.src.push_back(*extra);
+      o.src_rank.push_back(extra_rank);
     }
     o.dst = final_dst ? *final_dst : ws(n);
     o.dst_ws = final_dst ? final_ws : true;
@@ -295,6 +369,64 @@ struct Factorizer {
     Loc d = o.dst;
     ops.push_back(std::move(o));
     return d;
+  }
+
+  // One node of a ring reduction: reduce the node's leaves by its inner
+  // tree rooted at `holder`; the top operation also takes `inc` (the partial
+  // from the next node), last. Writes `dst` if given, else workspace.
+  Loc ring_node(const std::vector<int>& leaves, int lo, int holder, const Loc* inc, int inc_rank, uint64_t off,
+                uint64_t n, int stripe, int step, const Loc* dst, bool dst_ws) {
+    const int size = B[kr];
+    std::vector<int> lv = in_range(leaves, lo, lo + size);
+    Loc out = dst ? *dst : ws(n);
+    if (lv.empty()) {              // nothing to add here: only the arriving partial moves on
+      if (inc && !(inc->space == out.space && inc->addr == out.addr))
+        copy(*inc, inc_rank, out, holder, dst ? dst_ws : true, n, off, stripe, false, step);
+      return out;
+    }
+    RNode tree;
+    rtree(lv, holder, lo, kr + 1, tree);
+    if (tree.leaf >= 0) {
+      Loc s = user(p.send[tree.leaf], off);
+      if (inc) {
+        Op o;
+        o.kind = kReduce;
+        o.ring_step = step;
+        o.src = {s, *inc};
+        o.src_rank = {tree.leaf, inc_rank};
+        o.dst = out;
+        o.dst_ws = dst ? dst_ws : true;
+        o.dst_rank = holder;
+        o.count = n;
+        o.offset = off;
+        o.stripe = stripe;
+        ops.push_back(std::move(o));
+      } else if (!(s.space == out.space && s.addr == out.addr)) {
+        copy(s, tree.leaf, out, holder, dst ? dst_ws : true, n, off, stripe);
+      }
+      return out;
+    }
+    return emit_node(tree, off, n, stripe, &out, dst ? dst_ws : true, inc, inc_rank, step);
+  }
+
+  // Ring reduction (mirror of the ring multicast): the farthest node of the
+  // chain starts, each node adds its own leaves and forwards, the node of
+  // `o` finishes into `fin`.
+  void ring_reduce(const std::vector<int>& leaves, int o, uint64_t off, uint64_t n, int stripe, const Loc& fin,
+                   bool fin_ws) {
+    const int size = B[kr], lo0 = o / size * size;
+    std::vector<int> chain = ring_chain(o, leaves);
+    Loc inc;
+    int inc_rank = -1;
+    bool have = false;
+    for (int ci = int(chain.size()) - 1; ci >= 0; --ci) {
+      int holder = chain[ci] + (o - lo0);
+      inc = ring_node(leaves, chain[ci], holder, have ? &inc : nullptr, inc_rank, off, n, stripe, ci + 2, nullptr,
+                      true);
+      inc_rank = holder;
+      have = true;
+    }
+    ring_node(leaves, lo0, o, have ? &inc : nullptr, inc_rank, off, n, stripe, 1, &fin, fin_ws);
   }
 
   void reduction() {
@@ -316,6 +448,11 @@ struct Factorizer {
       int stripe = own.size() > 1 ? int(t) : 0;
       Loc fin = (o == j) ? user(p.recv[j], off) : ws(len);
       bool fin_ws = (o != j);
+      if (kr > 0) {
+        ring_reduce(leaves, o, off, len, stripe, fin, fin_ws);
+        if (o != j) copy(fin, o, user(p.recv[j], off), j, false, len, off, stripe);
+        continue;
+      }
       RNode tree;
       rtree(leaves, o, 0, 1, tree);
       if (tree.leaf >= 0) {
@@ -505,7 +642,17 @@ int build_plan(Comm& c) {
       if (b >= c.stripe && b % c.stripe == 0) ok = true;
     if (!ok) return fail(HICCL_ERR_INVALID_ARG, "stripe factor divides no group of the hierarchy");
   }
-  if (c.ring != 1) return fail(HICCL_ERR_UNSUPPORTED, "ring factorization is not built yet (ring must be 1)");
+  if (c.ring > 1) {
+    auto B = group_sizes(c.hier, c.P);
+    bool ok = c.P % c.ring == 0;
+    int kr = -1;
+    for (size_t k = 1; ok && k < B.size(); ++k)
+      if (B[k] == c.P / c.ring) kr = int(k);
+    if (!ok || kr < 0)
+      return fail(HICCL_ERR_INVALID_ARG, "ring length must make nranks/ring a group size of the hierarchy");
+    if (c.stripe > B[kr] || B[kr] % c.stripe)
+      return fail(HICCL_ERR_INVALID_ARG, "with a ring, the stripe factor must divide the ring's node size");
+  }
   Plan pl;
   uint64_t ws = 0;
   int rc = factorize_all(c, pl.tasks, ws);

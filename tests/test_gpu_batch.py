@@ -1,0 +1,83 @@
+"""Batching form on the GPU: many uneven collectives in one persistent launch, a captured hipGraph, or
+serial launches. Every result equals the oracle and is bit-identical to the same collective run alone."""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from tests import harness as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_2408_05962_amd import hiccl
+    hiccl.lib()
+    return torch
+
+
+def _mix(torch, n, seed, p=8, h=(2, 4)):
+    """n collectives of mixed type, dtype and size over p ranks; returns (specs, device buffers, host inputs)."""
+    import synth
+    from paper_2408_05962_amd import collectives as CO
+    rng = synth.choice_stream(seed, 1)
+    sizes = synth.log_uniform_sizes(seed, n, 4096, 4 << 20, p * 16)      # bytes per rank, multiple of p*16
+    items = []
+    for i in range(n):
+        name = H.SIX[int(rng.integers(0, 6))]
+        dtype = "int32" if rng.random() < 0.5 else "float32"
+        d = sizes[i] // 4 // p
+        if i % 5 == 0:
+            d += 3                                   # ragged chunk
+        s = [1, 2, 4][int(rng.integers(0, 3))]
+        m = [1, 2, 4][int(rng.integers(0, 3))]
+        sends = [np.asarray(x) for x in synth.rank_buffers("int32" if dtype == "int32" else "float32", 4, i, p,
+                                                           H.send_len(name, p, d))]
+        S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+        R = torch.zeros((p, H.recv_len(name, p, d)), dtype=S.dtype, device="cuda")
+        c = CO.make(name, p, dtype, [S[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=list(h),
+                    stripe=s, pipeline=m, tile_bytes=16384)
+        c.set_spin_limit(1 << 20)
+        items.append({"name": name, "dtype": dtype, "d": d, "s": s, "m": m, "comm": c, "S": S, "R": R,
+                      "sends": sends})
+    return items
+
+
+def _got(it, p=8):
+    out = it["R"].cpu().numpy()
+    ranks = [0] if it["name"] in ("reduce", "gather") else range(p)
+    return {r: out[r] for r in ranks}
+
+
+@pytest.mark.parametrize("mode", ["persistent", "graph", "serial", "persistent_sjf"])
+def test_batch_matches_oracle_and_alone(torch_cuda, mode):
+    torch = torch_cuda
+    from paper_2408_05962_amd import Batch
+    items = _mix(torch, 24, seed=11)
+    alone = []
+    for it in items:
+        it["R"].zero_()
+        it["comm"].run(torch.cuda.current_stream())
+        it["comm"].wait()
+        torch.cuda.synchronize()
+        alone.append(it["R"].cpu().numpy().copy())
+    b = Batch([it["comm"] for it in items], mode)
+    st = torch.cuda.current_stream()
+    for rep in range(3):
+        for it in items:
+            it["R"].zero_()
+        b.run(st)
+        b.wait()
+        torch.cuda.synchronize()
+        times = b.times_ns()
+        assert all(t > 0 for t in times)
+        for k, it in enumerate(items):
+            got = it["R"].cpu().numpy()
+            assert np.array_equal(got.view(np.uint32), alone[k].view(np.uint32)), (mode, rep, k, it["name"])
+            H.check_result(it["name"], _got(it), it["sends"], it["dtype"], h=[2, 4], s=it["s"])
+    b.close()
+    for it in items:
+        it["comm"].close()

@@ -29,7 +29,7 @@ def _host_inputs(name, p, d, dtype, seed):
 
 
 def _run(torch, name, p, h, dtype, d, s=1, m=1, mode="persistent", sends=None, seed=0, reps=1, tile=0, root=0,
-         op="sum", order="stage"):
+         op="sum", order="stage", ring=1):
     from paper_2408_05962_amd import collectives as CO
     if sends is None:
         sends = _host_inputs(name, p, d, dtype, seed)
@@ -39,7 +39,7 @@ def _run(torch, name, p, h, dtype, d, s=1, m=1, mode="persistent", sends=None, s
     send = [S[r] for r in range(p)]
     recv = [R[r] for r in range(p)]
     c = CO.make(name, p, dtype, send, recv, d, hierarchy=h, stripe=s, pipeline=m, exec_mode=mode, tile_bytes=tile,
-                root=root, op=op, order=order)
+                root=root, op=op, order=order, ring=ring)
     c.set_spin_limit(1 << 20)    # a stalled dependency fails the test within seconds
     st = torch.cuda.current_stream()
     outs = []
@@ -168,3 +168,16 @@ def test_config2_full_size(torch_cuda, name):
     got = R.cpu().numpy()
     c.close()
     H.check_result(name, _got(name, got, p, 0), sends, "float32", h=h, s=s, order_exact=True)
+
+
+@pytest.mark.parametrize("name", H.EIGHT)
+@pytest.mark.parametrize("h,ring,s,m", [([4, 4, 2], 4, 2, 4), ([4, 3], 4, 3, 5), ([8, 2], 8, 1, 8)])
+def test_ring_collectives(torch_cuda, name, h, ring, s, m):
+    """Hybrid ring + tree (Sec. 4.4) on the device: bit-exact data movement and tree/ring-order float32 sums."""
+    p = int(np.prod(h))
+    d = 1536 + 5 if name not in ("all_gather", "gather") else 4099
+    for dtype in ("int32", "float32"):
+        sends, outs = _run(torch_cuda, name, p, h, dtype, d, s=s, m=m, ring=ring, tile=8192, reps=2,
+                           seed=zlib.crc32(f"ring{name}{h}{dtype}".encode()) % 1000)
+        for out in outs:
+            H.check_result(name, _got(name, out, p, 0), sends, dtype, h=h, s=s, ring=ring)

@@ -1,0 +1,211 @@
+"""GPU precision form: bf16 and fp8-e4m3 payloads (per-256 power-of-two scales) through the C ABI.
+
+* the device payload conversion equals the oracle quantizer byte for byte;
+* collectives in a payload format equal the oracle's per-node widen / sum / narrow emulation byte for
+  byte (the requantization at every reduction node follows the schedule's tree);
+* the error against the float64 sum of the original float32 inputs is reported for every result.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import collectives as OC
+from oracle import quant as OQ
+from tests.conftest import gpu_available
+from tests import harness as H
+
+pytestmark = pytest.mark.gpu
+
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_2408_05962_amd import hiccl
+    hiccl.lib()
+    return torch
+
+
+def _payload_tensors(torch, X, dtype):
+    """Convert device float32 rows to payload rows on the device (library kernels)."""
+    from paper_2408_05962_amd import to_payload
+    p, n = X.shape
+    if dtype == "bfloat16":
+        Y = torch.empty((p, n), dtype=torch.int16, device="cuda")
+        for r in range(p):
+            to_payload("bfloat16", X[r], Y[r], None, n)
+        return Y, None
+    Y = torch.empty((p, n), dtype=torch.uint8, device="cuda")
+    Sc = torch.empty((p, n // 256), dtype=torch.float32, device="cuda")
+    for r in range(p):
+        to_payload("fp8_e4m3", X[r], Y[r], Sc[r], n)
+    return Y, Sc
+
+
+def test_payload_conversion_matches_oracle(torch_cuda):
+    torch = torch_cuda
+    import synth
+    n = 1 << 20
+    X = synth.device_buffers("float32_outliers", 31, 1, n)
+    x = X[0].cpu().numpy()
+    Y, _ = _payload_tensors(torch, X, "bfloat16")
+    assert np.array_equal(Y[0].cpu().numpy().view(np.uint16), OQ.f32_to_bf16_bits(x))
+    Y, Sc = _payload_tensors(torch, X, "fp8_e4m3")
+    c, s = OQ.fp8_quantize(x.astype(np.float64))
+    assert np.array_equal(Sc[0].cpu().numpy(), s)
+    assert np.array_equal(Y[0].cpu().numpy(), c)
+    # and back: widening is exact
+    from paper_2408_05962_amd import from_payload
+    Z = torch.empty(n, dtype=torch.float32, device="cuda")
+    from_payload("fp8_e4m3", Y[0], Sc[0], Z, n)
+    assert np.array_equal(Z.cpu().numpy().astype(np.float64), OQ.fp8_dequantize(c, s))
+
+
+def _run_payload(torch, name, dtype, X, h, s, m, d):
+    from paper_2408_05962_amd import collectives as CO
+    p = X.shape[0]
+    Y, Sc = _payload_tensors(torch, X, dtype)
+    rl = H.recv_len(name, p, d)
+    if dtype == "bfloat16":
+        R = torch.zeros((p, rl), dtype=torch.int16, device="cuda")
+        send = [Y[r] for r in range(p)]
+        recv = [R[r] for r in range(p)]
+        RS = None
+    else:
+        R = torch.zeros((p, rl), dtype=torch.uint8, device="cuda")
+        RS = torch.zeros((p, rl // 256), dtype=torch.float32, device="cuda")
+        send = [(Y[r], Sc[r]) for r in range(p)]
+        recv = [(R[r], RS[r]) for r in range(p)]
+    c = CO.make(name, p, dtype, send, recv, d, hierarchy=h, stripe=s, pipeline=m)
+    c.set_spin_limit(1 << 20)
+    c.run(torch.cuda.current_stream())
+    c.wait()
+    torch.cuda.synchronize()
+    c.close()
+    return Y, Sc, R, RS
+
+
+def _host_payload(dtype, Yr, Sr):
+    if dtype == "bfloat16":
+        return Yr.view(np.uint16)
+    return H.Fp8Buf(Yr, Sr)
+
+
+@pytest.mark.parametrize("dtype", ["bfloat16", "fp8_e4m3"])
+@pytest.mark.parametrize("name", ["all_reduce", "reduce_scatter", "reduce"])
+@pytest.mark.parametrize("h,s,m", [([2, 4, 2], 4, 2), ([4, 4], 2, 3), ([2, 4], 1, 1)])
+def test_payload_collectives_bit_exact(torch_cuda, dtype, name, h, s, m):
+    torch = torch_cuda
+    import synth
+    p = int(np.prod(h))
+    d = 256 * s * 4
+    X = synth.device_buffers("float32_outliers", 40 + p, p, d * p)
+    Y, Sc, R, RS = _run_payload(torch, name, dtype, X, h, s, m, d)
+    x = [v for v in X.cpu().numpy()]
+    yh, sh = Y.cpu().numpy(), (Sc.cpu().numpy() if Sc is not None else [None] * p)
+    pay = [_host_payload(dtype, yh[r], sh[r]) for r in range(p)]
+    # the device inputs equal the oracle's own quantization of the float32 inputs
+    for r in range(p):
+        ref = H.to_payload_host(x[r], dtype)
+        if dtype == "bfloat16":
+            assert np.array_equal(pay[r], ref)
+        else:
+            assert np.array_equal(pay[r].codes, ref.codes) and np.array_equal(pay[r].scales, ref.scales)
+    exp = H.tree_order_payload(name, pay, h, s)
+    rh, rsh = R.cpu().numpy(), (RS.cpu().numpy() if RS is not None else [None] * p)
+    exact = H.expected(name, x)
+    scale = H.abs_scale(name, x)
+    for r, e in exp.items():
+        got = _host_payload(dtype, rh[r], rsh[r])
+        if dtype == "bfloat16":
+            assert np.array_equal(got, e), f"{name} {dtype} rank {r}"
+        else:
+            assert np.array_equal(got.codes, e.codes) and np.array_equal(got.scales, e.scales), f"{name} {dtype} rank {r}"
+        rep = OC.error_report(H.payload_values(got, dtype), exact[r], scale[r])
+        assert rep["scaled"] < (0.05 if dtype == "bfloat16" else 0.5)
+
+
+@pytest.mark.parametrize("dtype", ["float32", "bfloat16", "fp8_e4m3"])
+@pytest.mark.parametrize("name", ["all_reduce", "reduce_scatter"])
+def test_config3_full_size_sampled(torch_cuda, dtype, name):
+    """16 ranks as {2,4,2}, 2^28 elements per rank ~ N(0,1) with 1 % of entries x 1e3, stripe 4,
+    pipeline 8: results checked on sampled 256-element blocks of every chunk against the oracle
+    (order-exact), and the error against float64 reported per format."""
+    torch = torch_cuda
+    import synth
+    from paper_2408_05962_amd import collectives as CO
+    p, h, s, m = 16, [2, 4, 2], 4, 8
+    n = 1 << 28
+    d = n // p
+    X = synth.device_buffers("float32_outliers", 77, p, n)
+    rng = np.random.default_rng(5)
+    blocks = sorted(set(rng.integers(0, d // 256, 6).tolist()) | {0, d // 256 - 1})
+    if dtype == "float32":
+        rl = H.recv_len(name, p, d)
+        R = torch.zeros((p, rl), dtype=torch.float32, device="cuda")
+        c = CO.make(name, p, "float32", [X[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=h,
+                    stripe=s, pipeline=m)
+        c.run(torch.cuda.current_stream())
+        c.wait()
+        torch.cuda.synchronize()
+        c.close()
+        Y = Sc = RS = None
+    else:
+        Y, Sc, R, RS = _run_payload(torch, name, dtype, X, h, s, m, d)
+    stats = []
+    for j in (0, 5, p - 1):              # sampled chunks (the chunk rank j reduces)
+        for b in blocks:
+            lo = j * d + b * 256
+            xs = [X[r, lo:lo + 256].cpu().numpy() for r in range(p)]
+            exact = OC.combine(xs, "sum")
+            scale = OC.abs_sum(xs)
+            # oracle: the same block through the owner's tree (stripes are whole 256 blocks here)
+            from oracle import tree as OT
+            off_in_chunk = b * 256
+            own = OT.stripe_owners(j, range(p), h, s)
+            pieces = OT.split(d, s, H.ALIGN[dtype] if dtype != "float32" else 4)
+            t = next(i for i, (o, ln) in enumerate(pieces) if o <= off_in_chunk < o + ln)
+            root = own[t]
+            if dtype == "float32":
+                want = OT.tree_reduce(dict(enumerate(np.asarray(v, np.float32) for v in xs)), range(p), root, h,
+                                      OT.sum_f32)
+            else:
+                ys = [Y[r, lo:lo + 256].cpu().numpy() for r in range(p)]
+                ss = [Sc[r, lo // 256:lo // 256 + 1].cpu().numpy() if Sc is not None else None for r in range(p)]
+                pay = dict(enumerate(_host_payload(dtype, ys[r], ss[r]) for r in range(p)))
+                want = OT.tree_reduce(pay, range(p), root, h, H._node(dtype))
+            # where the result sits: rank j's chunk (RS) or every rank's copy of chunk j (AR)
+            rank = j
+            col = b * 256 if name == "reduce_scatter" else lo
+            if dtype == "float32":
+                got = R[rank, col:col + 256].cpu().numpy()
+                assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+                gv = got.astype(np.float64)
+            else:
+                gy = R[rank, col:col + 256].cpu().numpy()
+                gs = RS[rank, col // 256:col // 256 + 1].cpu().numpy() if RS is not None else None
+                got = _host_payload(dtype, gy, gs)
+                if dtype == "bfloat16":
+                    assert np.array_equal(got, want)
+                else:
+                    assert np.array_equal(got.codes, want.codes) and np.array_equal(got.scales, want.scales)
+                gv = H.payload_values(got, dtype)
+            stats.append(OC.error_report(gv, exact, scale))
+            if name == "all_reduce" and dtype == "float32":
+                other = R[(j + 3) % p, col:col + 256].cpu().numpy()
+                assert np.array_equal(other.view(np.uint32), got.view(np.uint32))
+    worst = {k: max(st[k] for st in stats) for k in stats[0]}
+    if dtype == "float32":
+        assert worst["scaled"] <= H.TOL_F32
+    os.makedirs(OUT, exist_ok=True)
+    with open(os.path.join(OUT, f"precision_{name}_{dtype}.json"), "w") as f:
+        json.dump({"collective": name, "payload": dtype, "ranks": p, "elements_per_rank": n,
+                   "sampled_blocks": len(stats), "error_vs_float64": worst}, f)
+    print(f"\n{name} {dtype}: error vs float64 on {len(stats)} sampled blocks: {worst}", flush=True)
+    del X, R
+    torch.cuda.empty_cache()

@@ -30,13 +30,15 @@ def _inputs(name, p, d, dtype, seed):
     return [rng.standard_normal(n).astype(np.float32) for _ in range(p)]
 
 
-def host_run(name, p, h, dtype, d, s=1, m=1, root=0, op="sum", seed=0, norders=3, tile=0, form="listing"):
+def host_run(name, p, h, dtype, d, s=1, m=1, root=0, op="sum", seed=0, norders=3, tile=0, form="listing", ring=1):
     _lib()
     from paper_2408_05962_amd import collectives as CO
     sends = _inputs(name, p, d, dtype, seed)
     recvs = [np.full(H.recv_len(name, p, d), -7, H.NP[dtype]) for _ in range(p)]
     c = CO.make(name, p, dtype, sends, recvs, d, hierarchy=h, stripe=s, pipeline=m, root=root, op=op, tile_bytes=tile,
-                form=form)
+                form=form, init=False)
+    c.set_ring(ring)
+    c.init()
     c.validate_host(seed=seed, norders=norders)
     info = c.plan_info()
     c.close()
@@ -93,3 +95,54 @@ def test_config1_shape():
     assert info["nstages"] == 4
     assert lb[1] == 512 * 1024 and lb[2] == 1024 * 1024      # top 512 KiB, intra-node 1 MiB
     assert rd + wr == 15 * n * 4                              # 15 S executed bytes
+
+
+@pytest.mark.parametrize("name", H.EIGHT)
+@pytest.mark.parametrize("dtype", ["int32", "float32"])
+@pytest.mark.parametrize("h,ring,s,m", [([4, 3], 4, 3, 5), ([4, 4, 2], 4, 2, 2), ([2, 4, 2], 2, 4, 3), ([4, 2], 4, 1, 1),
+                                        ([8, 2], 8, 2, 4)])
+def test_ring_plans_match_oracle(name, dtype, h, ring, s, m):
+    p = int(np.prod(h))
+    d = 24 * s if name not in ("all_gather", "gather") else 40 * s
+    seed = zlib.crc32(f"ring{name}{dtype}{h}".encode()) % 1000
+    sends, got, info = host_run(name, p, h, dtype, d, s=s, m=m, seed=seed, ring=ring)
+    H.check_result(name, got, sends, dtype, h=h, s=s, ring=ring)
+
+
+def test_ring_broadcast_stages_and_rails():
+    """ring(4), stripe(3) on 4 nodes x 3 GPUs: five stages (Fig. 6(b)) and the same hops as the oracle."""
+    from oracle import tree as OT
+    _lib()
+    from paper_2408_05962_amd import Comm
+    p, n = 12, 96
+    send = [np.zeros(n, np.float32) for _ in range(p)]
+    recv = [np.zeros(n, np.float32) for _ in range(p)]
+    c = Comm(p, "float32")
+    c.add_multicast(send, recv, n, 0, list(range(p)))
+    c.set_hierarchy([4, 3])
+    c.set_stripe(3)
+    c.set_ring(4)
+    c.init()
+    assert c.plan_info()["nstages"] == 5
+    lib_hops = sorted((t["src_rank"][0], t["dst_rank"]) for t in c.plan_tasks() if t["src_rank"][0] != t["dst_rank"])
+    hops, nst = OT.ring_multicast_hops(0, range(p), [4, 3], 4, s=3)
+    assert nst == 5
+    assert lib_hops == sorted((hp.src, hp.dst) for hp in hops)
+    ring_steps = {t["ring_step"] for t in c.plan_tasks()}
+    assert ring_steps == {0, 1, 2, 3}
+    c.close()
+
+
+def test_ring_one_equals_tree_plan():
+    _lib()
+    from paper_2408_05962_amd import collectives as CO
+    p, d = 16, 64
+    sends = [np.zeros(d * p, np.float32) for _ in range(p)]
+    recvs = [np.zeros(d * p, np.float32) for _ in range(p)]
+    a = CO.make("all_reduce", p, "float32", sends, recvs, d, hierarchy=[2, 4, 2], stripe=4, pipeline=2)
+    b = CO.make("all_reduce", p, "float32", sends, recvs, d, hierarchy=[2, 4, 2], stripe=4, pipeline=2, init=False)
+    b.set_ring(1)
+    b.init()
+    ta, tb = a.plan_tasks(), b.plan_tasks()
+    assert [(t["kind"], t["src_rank"], t["dst_rank"], t["count"]) for t in ta] == \
+        [(t["kind"], t["src_rank"], t["dst_rank"], t["count"]) for t in tb]
