@@ -72,6 +72,210 @@ def cpu_baseline(budget_s: float = 20.0) -> dict:
                       f"numpy on one core of {os.cpu_count()})"}
 
 
+# ------------------------------------------------------------------ batching (config 4)
+BATCH_P, BATCH_H = 8, [2, 4]
+SIZE_CLASSES = [(4 << 10, 64 << 10), (64 << 10, 1 << 20), (1 << 20, 16 << 20), (16 << 20, 64 << 20)]
+
+
+def _size_class(nbytes):
+    for i, (lo, hi) in enumerate(SIZE_CLASSES):
+        if nbytes < hi:
+            return i
+    return len(SIZE_CLASSES) - 1
+
+
+def _mk(torch, CO, name, p, h, dtype, per_rank_bytes, seed, s=1, m=1, tile=0, grid=0, ring=1):
+    """A communicator with its own device buffers for a collective of `per_rank_bytes` (largest buffer)."""
+    import synth
+    es = 2 if dtype == "bfloat16" else 4
+    d = max(1, per_rank_bytes // es // p)
+    if dtype == "bfloat16":
+        d = max(8, d // 8 * 8)
+    kind = "int32" if dtype == "int32" else "float32"
+    snd = synth.device_buffers(kind, seed, p, send_len(name, p, d))
+    if dtype == "bfloat16":
+        snd = snd.to(torch.bfloat16).view(torch.int16)
+    rcv = torch.zeros((p, recv_len(name, p, d)), dtype=snd.dtype, device="cuda")
+    c = CO.make(name, p, dtype, [snd[r] for r in range(p)], [rcv[r] for r in range(p)], d, hierarchy=h, stripe=s,
+                pipeline=m, tile_bytes=tile, grid=grid, ring=ring)
+    return c, snd, rcv, d * p * es
+
+
+def tune_table(torch, seed=9):
+    """Autotuned (stripe, pipeline, tile) per (collective, size class), on buffers of a different seed."""
+    from paper_2408_05962_amd import autotune
+    from paper_2408_05962_amd import collectives as CO
+    table = {}
+    st = torch.cuda.current_stream()
+    for name in SIX:
+        for ci, (lo, hi) in enumerate(SIZE_CLASSES):
+            size = int((lo * hi) ** 0.5) // (BATCH_P * 16) * (BATCH_P * 16)
+            c, snd, rcv, _ = _mk(torch, CO, name, BATCH_P, BATCH_H, "float32", size, seed * 100 + ci)
+            r = autotune(c, [1, 2, 4], [1, 2, 4, 8], [16384, 65536], reps=3, stream=st)
+            table[(name, ci)] = (r["stripe"], r["pipeline"], r["tile_bytes"])
+            c.close()
+            del snd, rcv
+    return table
+
+
+def batch_bench(torch, n=512, seed=4, reps=3):
+    import numpy as np
+
+    import synth
+    from paper_2408_05962_amd import Batch
+    from paper_2408_05962_amd import collectives as CO
+    t_tune = time.perf_counter()
+    table = tune_table(torch)
+    t_tune = time.perf_counter() - t_tune
+    rng = synth.choice_stream(seed, 2)
+    sizes = synth.log_uniform_sizes(seed, n, 4 << 10, 64 << 20, BATCH_P * 16)
+    items = []
+    t_plan = time.perf_counter()
+    for i in range(n):
+        name = SIX[int(rng.integers(0, 6))]
+        dtype = "int32" if rng.random() < 0.5 else "float32"
+        s, m, tile = table[(name, _size_class(sizes[i]))]
+        c, snd, rcv, S = _mk(torch, CO, name, BATCH_P, BATCH_H, dtype, sizes[i], 5000 + i, s, m, tile)
+        info = c.plan_info()
+        items.append((c, snd, rcv, S, info["hbm_read"] + info["hbm_written"]))
+    t_plan = time.perf_counter() - t_plan
+    comms = [it[0] for it in items]
+    total_S = sum(it[3] for it in items)
+    total_exec = sum(it[4] for it in items)
+    st = torch.cuda.current_stream()
+    out = {"collectives": n, "ranks": BATCH_P, "hierarchy": BATCH_H, "sum_S_bytes": total_S,
+           "sum_exec_bytes": total_exec, "tune_s": round(t_tune, 2), "plan_s": round(t_plan, 2),
+           "tuned": {f"{k[0]}/{SIZE_CLASSES[k[1]][0]}": v for k, v in table.items()}}
+    for mode in ("serial", "graph", "persistent", "persistent_sjf"):
+        b = Batch(comms, mode)
+        b.run(st)
+        b.wait()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        spans, lat = [], []
+        for _ in range(reps):
+            e0.record(st)
+            b.run(st)
+            e1.record(st)
+            b.wait()
+            torch.cuda.synchronize()
+            spans.append(e0.elapsed_time(e1))
+            lat.append(np.asarray(b.times_ns(), dtype=np.float64) / 1e3)
+        b.close()
+        ms = float(np.median(spans))
+        L = np.concatenate(lat)
+        out[mode] = {"makespan_ms": round(ms, 3), "algbw_GBps": round(total_S / ms / 1e6, 1),
+                     "exec_GBps": round(total_exec / ms / 1e6, 1),
+                     "hbm_frac": round(total_exec / ms / 1e6 / PEAK_HBM, 4),
+                     "latency_us_p50": round(float(np.percentile(L, 50)), 1),
+                     "latency_us_p99": round(float(np.percentile(L, 99)), 1)}
+    for c in comms:
+        c.close()
+    return out
+
+
+# ------------------------------------------------------------------- serving (config 5)
+SERVE_HIERS = [[2, 4], [2, 4, 2], [4, 4]]
+
+
+def serve_bench(torch, ntemplates=48, nreq=400, fractions=(0.25, 0.5, 0.75, 0.9, 1.2), slots=4,
+                budget=200 * 10 ** 9, seed=8):
+    """Poisson stream of collective requests over resident request templates.
+
+    Templates are drawn from the config's mix (type uniform over the six, hierarchy from {2x4, 2x4x2, 4x4},
+    per-rank size log-uniform in [1 KiB, 256 MiB], dtype from {int32, float32, bf16}); each keeps its
+    buffers and schedule resident. A request picks a template; it is admitted when a slot and budget are
+    free and its template is idle. Latency = arrival to completion (host clock)."""
+    import numpy as np
+
+    import synth
+    from paper_2408_05962_amd import Server
+    from paper_2408_05962_amd import collectives as CO
+    rng = synth.choice_stream(seed, 3)
+    sizes = synth.log_uniform_sizes(seed, ntemplates, 1 << 10, 256 << 20, 16 * 16)
+    temps = []
+    for i in range(ntemplates):
+        name = SIX[int(rng.integers(0, 6))]
+        h = SERVE_HIERS[int(rng.integers(0, 3))]
+        p = int(np.prod(h))
+        dtype = ["int32", "float32", "bfloat16"][int(rng.integers(0, 3))]
+        s = 4 if p == 16 else 2
+        m = 8 if sizes[i] >= (1 << 20) else 1
+        c, snd, rcv, S = _mk(torch, CO, name, p, h, dtype, sizes[i], 7000 + i, s, m, 65536)
+        c.set_claim(1, 4)    # one tile queue: progress holds however many of its workgroups are resident
+        foot = snd.numel() * snd.element_size() + rcv.numel() * rcv.element_size() + c.workspace_size()
+        c.run(torch.cuda.current_stream())
+        c.wait()
+        temps.append({"comm": c, "snd": snd, "rcv": rcv, "S": S, "foot": foot, "name": name, "p": p})
+    torch.cuda.synchronize()
+
+    def run_stream(arrivals, picks, nslots):
+        # FIFO gives each collective the whole device; concurrent slots share it
+        for tpl in temps:
+            tpl["comm"].set_grid(0 if nslots == 1 else shared_grid)
+        srv = Server(budget, nslots)
+        busy = [False] * len(temps)
+        queue, inflight, lat = [], {}, []
+        t0 = time.perf_counter()
+        i = 0
+        n = len(arrivals)
+        while len(lat) < n:
+            now = time.perf_counter() - t0
+            while i < n and arrivals[i] <= now:
+                queue.append((arrivals[i], picks[i]))
+                i += 1
+            # admit in arrival order while a slot, budget and the template are free
+            k = 0
+            while k < len(queue):
+                arr, tp = queue[k]
+                if busy[tp]:
+                    k += 1
+                    continue
+                tk = srv.admit(temps[tp]["foot"])
+                if tk is None:
+                    break
+                srv.launch(tk, temps[tp]["comm"])
+                busy[tp] = True
+                inflight[tk] = (arr, tp)
+                queue.pop(k)
+            srv.progress()
+            for tk in list(inflight):
+                done, _ = srv.poll(tk)
+                if done:
+                    arr, tp = inflight.pop(tk)
+                    busy[tp] = False
+                    lat.append(time.perf_counter() - t0 - arr)
+            if not queue and not inflight and i < n:
+                time.sleep(max(0.0, min(arrivals[i] - (time.perf_counter() - t0), 0.001)))
+        span = time.perf_counter() - t0
+        srv.drain()
+        srv.close()
+        return span, np.asarray(lat)
+
+    props = torch.cuda.get_device_properties(0)
+    shared_grid = max(1, 3 * props.multi_processor_count // slots)
+    g = synth.choice_stream(seed, 4)
+    picks = g.integers(0, len(temps), nreq)
+    # closed loop: everything arrives at once -> sustained service rate mu
+    span, _ = run_stream(np.zeros(nreq), picks, slots)
+    mu = nreq / span
+    out = {"templates": ntemplates, "requests_per_rate": nreq, "slots": slots, "budget_bytes": budget,
+           "mu_req_per_s": round(mu, 1), "rates": []}
+    for f in fractions:
+        lam = f * mu
+        arrivals = np.cumsum(g.exponential(1.0 / lam, nreq))
+        row = {"fraction_of_mu": f, "lambda_req_per_s": round(lam, 1)}
+        for label, ns in (("continuous", slots), ("fifo", 1)):
+            span, lat = run_stream(arrivals, picks, ns)
+            Sb = sum(temps[tp]["S"] for tp in picks)
+            row[label] = {"throughput_req_per_s": round(nreq / span, 1), "algbw_GBps": round(Sb / span / 1e9, 2),
+                          "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                          "latency_ms_p99": round(float(np.percentile(lat, 99)) * 1e3, 3)}
+        out["rates"].append(row)
+    for tpl in temps:
+        tpl["comm"].close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +285,8 @@ def main():
     ap.add_argument("--tile", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--batch", action="store_true", help="also measure the batching form (512 collectives)")
+    ap.add_argument("--serve", action="store_true", help="also measure the serving form (Poisson requests)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the virtual ranks of the hierarchy "
@@ -188,10 +394,18 @@ def main():
         "per_collective": per,
         "empirical_copy_GBps": round(copy_gbps, 1),
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     for c in comms.values():
         c.close()
+    del bufs
+    torch.cuda.empty_cache()
+    if args.batch:
+        out["batching"] = batch_bench(torch)
+        torch.cuda.empty_cache()
+    if args.serve:
+        out["serving"] = serve_bench(torch)
+        torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

@@ -178,6 +178,10 @@ int hiccl_run(hiccl_comm_t comm, void* stream);
  * reused. Returns TIMEOUT if the executor gave up a dependency wait. */
 int hiccl_wait(hiccl_comm_t comm);
 
+/* Workgroups of the next runs (0 = fill the device), without re-planning.
+ * A smaller grid lets several collectives share the device at once. */
+int hiccl_set_grid(hiccl_comm_t comm, int grid);
+
 /* Tile claiming of the persistent executor (not a paper parameter): the
  * task table is dealt round-robin into `queues` queues (1..8; 0 = 8), each
  * claimed `batch` tiles per atomic (0 = 4). A single queue keeps progress

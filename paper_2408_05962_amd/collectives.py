@@ -85,6 +85,53 @@ def compose(comm: Comm, name: str, send, recv, d: int, root: int = 0, op: str = 
     return comm
 
 
+MULTI = ("broadcast", "reduce", "all_gather", "reduce_scatter", "all_reduce_bcast")
+
+
+def compose_multi(comm: Comm, name: str, send, recv, scratch, d: int, root: int = 0, op: str = "sum"):
+    """Register a two-step row of Table 2 (read right to left, the dot being a fence) with a
+    per-rank scratch buffer of d*p elements holding the intermediate:
+
+      broadcast        = All-gather . Scatter
+      reduce           = Gather . Reduce-scatter
+      all_gather       = Broadcast . Gather
+      reduce_scatter   = Scatter . Reduce
+      all_reduce_bcast = Broadcast . Reduce
+    """
+    p, dt = comm.nranks, comm.dtype
+    U = list(range(p))
+    at = lambda b, e: _at(b, e, dt)  # noqa: E731
+    if name == "broadcast":
+        for j in U:                                   # scatter chunk j of the root's buffer to rank j
+            comm.add_multicast([at(send[r], j * d) for r in U], scratch, d, root, [j])
+        comm.add_fence()
+        for i in U:                                   # all-gather the chunks
+            comm.add_multicast(scratch, [at(recv[r], i * d) for r in U], d, i, U)
+    elif name == "reduce":
+        for j in U:                                   # reduce-scatter into the scratch buffers
+            comm.add_reduction([at(send[r], j * d) for r in U], scratch, d, U, j, op)
+        comm.add_fence()
+        for i in U:                                   # gather at the root
+            comm.add_multicast(scratch, [at(recv[r], i * d) for r in U], d, i, [root])
+    elif name == "all_gather":
+        for i in U:                                   # gather at the root's scratch
+            comm.add_multicast(send, [at(scratch[r], i * d) for r in U], d, i, [root])
+        comm.add_fence()
+        comm.add_multicast(scratch, recv, d * p, root, U)   # broadcast it
+    elif name == "reduce_scatter":
+        comm.add_reduction(send, scratch, d * p, U, root, op)   # reduce at the root
+        comm.add_fence()
+        for j in U:                                   # scatter chunk j to rank j
+            comm.add_multicast([at(scratch[r], j * d) for r in U], recv, d, root, [j])
+    elif name == "all_reduce_bcast":
+        comm.add_reduction(send, scratch, d * p, U, root, op)
+        comm.add_fence()
+        comm.add_multicast(scratch, recv, d * p, root, U)
+    else:
+        raise ValueError(f"unknown two-step composition {name!r}")
+    return comm
+
+
 def make(name: str, p: int, dtype, send, recv, d: int, hierarchy=None, stripe: int = 1, pipeline: int = 1,
          root: int = 0, op: str = "sum", form: str = "listing", exec_mode: str = "persistent", tile_bytes: int = 0,
          grid: int = 0, order: str = "stage", init: bool = True, ring: int = 1) -> Comm:

@@ -880,6 +880,19 @@ int hiccl_run(hiccl_comm_t comm, void* stream) {
   return HICCL_SUCCESS;
 }
 
+int hiccl_set_grid(hiccl_comm_t comm, int grid) {
+  if (!comm) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator");
+  if (grid < 0) return fail(HICCL_ERR_INVALID_ARG, "grid must be >= 0");
+  Comm& c = comm->c;
+  c.exec.grid = grid;
+  if (c.dev) {
+    Exe& ex = c.dev->exe;
+    ex.grid = std::min<int>(device_grid(grid, ex.narrow), std::max<uint32_t>(1u, ex.ntiles));
+    ex.queues = uint32_t(std::max(1, std::min<int>(c.exec.queues, std::min<int>(kMaxQueues, ex.grid))));
+  }
+  return HICCL_SUCCESS;
+}
+
 int hiccl_wait(hiccl_comm_t comm) {
   if (!comm) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator");
   Comm& c = comm->c;

@@ -76,6 +76,7 @@ def lib():
             "hiccl_set_exec": [vp, i, sz, i, i],
             "hiccl_set_spin_limit": [vp, C.c_uint32],
             "hiccl_set_claim": [vp, i, i],
+            "hiccl_set_grid": [vp, i],
             "hiccl_init": [vp],
             "hiccl_workspace_size": [vp, C.POINTER(sz)],
             "hiccl_set_workspace": [vp, vp, sz],
@@ -202,6 +203,9 @@ class Comm:
     def set_exec(self, mode="persistent", tile_bytes=0, grid=0, order="stage"):
         return check(lib().hiccl_set_exec(self.h, EXEC.get(mode, mode), int(tile_bytes), int(grid),
                                           ORDER.get(order, order)))
+
+    def set_grid(self, grid=0):
+        return check(lib().hiccl_set_grid(self.h, int(grid)))
 
     def set_claim(self, queues=0, batch=0):
         return check(lib().hiccl_set_claim(self.h, int(queues), int(batch)))

@@ -146,3 +146,41 @@ def test_ring_one_equals_tree_plan():
     ta, tb = a.plan_tasks(), b.plan_tasks()
     assert [(t["kind"], t["src_rank"], t["dst_rank"], t["count"]) for t in ta] == \
         [(t["kind"], t["src_rank"], t["dst_rank"], t["count"]) for t in tb]
+
+
+@pytest.mark.parametrize("name", ["broadcast", "reduce", "all_gather", "reduce_scatter", "all_reduce_bcast"])
+@pytest.mark.parametrize("dtype", ["int32", "float32"])
+@pytest.mark.parametrize("h,s,m", [([2, 4, 2], 4, 2), ([2, 3], 3, 1), ([4, 4], 1, 3)])
+def test_two_step_compositions(name, dtype, h, s, m):
+    """The multi-step rows of Table 2 through the library equal the direct definitions (and, for
+    sums, the oracle's own step interpreter running the same composition)."""
+    _lib()
+    from oracle import steps as OS
+    from paper_2408_05962_amd import Comm
+    from paper_2408_05962_amd import collectives as CO
+    p = int(np.prod(h))
+    d = 24
+    seed = zlib.crc32(f"multi{name}{dtype}{h}".encode()) % 1000
+    base = "all_reduce" if name == "all_reduce_bcast" else name
+    sends = _inputs(base, p, d, dtype, seed)
+    recvs = [np.full(H.recv_len(base, p, d), -7, H.NP[dtype]) for _ in range(p)]
+    scratch = [np.zeros(d * p, H.NP[dtype]) for _ in range(p)]
+    c = Comm(p, dtype)
+    CO.compose_multi(c, name, sends, recvs, scratch, d, root=p - 1)
+    c.set_hierarchy(h)
+    c.set_stripe(s)
+    c.set_pipeline(m)
+    c.init()
+    c.validate_host(seed=seed, norders=3)
+    c.close()
+    root = p - 1
+    ranks = [root] if base in ("reduce",) else range(p)
+    exp = H.expected(base, sends, root)
+    mem = OS.run(OS.Memory(OS.buffers_for(base, p, d, sends, "multi")), OS.compose(base if name != "all_reduce_bcast" else name, p, d, root=root, form="multi"))
+    for r in ranks:
+        y = exp[r]
+        if dtype == "int32":
+            assert np.array_equal(recvs[r], y), (name, r)
+        else:
+            assert np.max(np.abs(recvs[r] - y) / np.maximum(1, np.abs(y))) < 1e-5, (name, r)
+        assert np.allclose(mem.result(f"y{r}", np.float64 if dtype == "float32" else np.int32), y)

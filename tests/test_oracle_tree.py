@@ -199,3 +199,18 @@ def test_sum_f32_is_left_to_right():
     c = np.array([-1e8], np.float32)
     assert T.sum_f32([a, b, c])[0] == np.float32(0.0)      # (1e8 + 1) rounds back to 1e8
     assert T.sum_f32([a, c, b])[0] == np.float32(1.0)
+
+
+@pytest.mark.parametrize("h", [[2, 2, 3], [2, 4, 2], [4, 4], [3, 2, 2]])
+def test_reduction_is_the_mirror_of_the_multicast(h):
+    """A full-leaf reduction moves data along exactly the reversed hops of the multicast from the same
+    root (Sec. 4.2 describes one tree; the worked {2,2,3} broadcast of Sec. 4.3 fixes its hops)."""
+    p = int(np.prod(h))
+    for root in (0, p - 1, p // 2 + 1):
+        mc = {(hp.dst, hp.src) for hp in T.multicast_hops(root, range(p), h)}
+        red = set()
+        for nd in T.reduction_nodes(T.reduction_tree(range(p), root, h)):
+            for ch in nd.children:
+                if T.host(ch) != nd.host:
+                    red.add((T.host(ch), nd.host))
+        assert red == mc, (h, root)
