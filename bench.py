@@ -103,7 +103,7 @@ def _mk(torch, CO, name, p, h, dtype, per_rank_bytes, seed, s=1, m=1, tile=0, gr
 
 def tune_table(torch, seed=9):
     """Autotuned (stripe, pipeline, tile) per (collective, size class), on buffers of a different seed."""
-    from paper_2408_05962_amd import autotune
+    from paper_2408_05962_amd import autotune_model
     from paper_2408_05962_amd import collectives as CO
     table = {}
     st = torch.cuda.current_stream()
@@ -111,7 +111,7 @@ def tune_table(torch, seed=9):
         for ci, (lo, hi) in enumerate(SIZE_CLASSES):
             size = int((lo * hi) ** 0.5) // (BATCH_P * 16) * (BATCH_P * 16)
             c, snd, rcv, _ = _mk(torch, CO, name, BATCH_P, BATCH_H, "float32", size, seed * 100 + ci)
-            r = autotune(c, [1, 2, 4], [1, 2, 4, 8], [16384, 65536], reps=3, stream=st)
+            r = autotune_model(c, [1, 2, 4], [1, 2, 4, 8], [16384, 65536], reps=3, anchors=4, top=3, stream=st)
             table[(name, ci)] = (r["stripe"], r["pipeline"], r["tile_bytes"])
             c.close()
             del snd, rcv
@@ -170,6 +170,92 @@ def batch_bench(torch, n=512, seed=4, reps=3):
                      "latency_us_p99": round(float(np.percentile(L, 99)), 1)}
     for c in comms:
         c.close()
+    return out
+
+
+# ----------------------------------------------------------------- precision (config 3)
+def precision_bench(torch, reps=5, n=1 << 28, sample_blocks=64):
+    """All-Reduce and Reduce-Scatter over 16 ranks as {2,4,2}, 2^28 elements per rank ~ N(0,1) with 1 % of
+    entries x 1e3, stripe 4, pipeline 8; payload float32 vs bf16 vs fp8-e4m3 (per-256 power-of-two
+    scales), float32 accumulation. Error vs the float64 sum of the original float32 inputs on sampled
+    256-element blocks of every rank's chunk."""
+    import numpy as np
+
+    import synth
+    from oracle import collectives as OC
+    from oracle import quant as OQ
+    from paper_2408_05962_amd import collectives as CO
+    from paper_2408_05962_amd import from_payload, to_payload
+    p, h, s, m = 16, [2, 4, 2], 4, 8
+    d = n // p
+    X = synth.device_buffers("float32_outliers", 301, p, n)
+    st = torch.cuda.current_stream()
+    rng = np.random.default_rng(1)
+    out = {"ranks": p, "elements_per_rank": n, "stripe": s, "pipeline": m, "results": []}
+    for name in ("all_reduce", "reduce_scatter"):
+        rl = recv_len(name, p, d)
+        for dtype in ("float32", "bfloat16", "fp8_e4m3"):
+            if dtype == "float32":
+                send = [X[r] for r in range(p)]
+                R = torch.zeros((p, rl), dtype=torch.float32, device="cuda")
+                recv = [R[r] for r in range(p)]
+                Y = Sc = RS = None
+            elif dtype == "bfloat16":
+                Y = torch.empty((p, n), dtype=torch.int16, device="cuda")
+                for r in range(p):
+                    to_payload("bfloat16", X[r], Y[r], None, n, st)
+                R = torch.zeros((p, rl), dtype=torch.int16, device="cuda")
+                send, recv, Sc, RS = [Y[r] for r in range(p)], [R[r] for r in range(p)], None, None
+            else:
+                Y = torch.empty((p, n), dtype=torch.uint8, device="cuda")
+                Sc = torch.empty((p, n // 256), dtype=torch.float32, device="cuda")
+                for r in range(p):
+                    to_payload("fp8_e4m3", X[r], Y[r], Sc[r], n, st)
+                R = torch.zeros((p, rl), dtype=torch.uint8, device="cuda")
+                RS = torch.zeros((p, rl // 256), dtype=torch.float32, device="cuda")
+                send = [(Y[r], Sc[r]) for r in range(p)]
+                recv = [(R[r], RS[r]) for r in range(p)]
+            c = CO.make(name, p, dtype, send, recv, d, hierarchy=h, stripe=s, pipeline=m)
+            info = c.plan_info()
+            c.run(st)
+            c.wait()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(reps):
+                c.run(st)
+            e1.record(st)
+            c.wait()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            c.close()
+            # errors on sampled blocks: widen the result rows on the device, compare on the host
+            errs = []
+            for j in rng.integers(0, p, 4):
+                blocks = rng.integers(0, d // 256, sample_blocks // 4)
+                for b in blocks:
+                    lo = int(j) * d + int(b) * 256
+                    col = int(b) * 256 if name == "reduce_scatter" else lo
+                    xs = [X[r, lo:lo + 256].cpu().numpy() for r in range(p)]
+                    exact = OC.combine(xs, "sum")
+                    if dtype == "float32":
+                        got = R[int(j), col:col + 256].cpu().numpy().astype(np.float64)
+                    elif dtype == "bfloat16":
+                        got = OQ.bf16_bits_to_f32(R[int(j), col:col + 256].cpu().numpy().view(np.uint16)).astype(np.float64)
+                    else:
+                        got = OQ.fp8_dequantize(R[int(j), col:col + 256].cpu().numpy(),
+                                                RS[int(j), col // 256:col // 256 + 1].cpu().numpy())
+                    errs.append(OC.error_report(got, exact, OC.abs_sum(xs)))
+            worst = {k: max(e[k] for e in errs) for k in errs[0]}
+            exec_b = info["hbm_read"] + info["hbm_written"]
+            out["results"].append({"collective": name, "payload": dtype, "ms": round(ms, 3),
+                                   "algbw_GBps": round(n * 4 / ms / 1e6, 1),
+                                   "exec_bytes": exec_b, "exec_GBps": round(exec_b / ms / 1e6, 1),
+                                   "hbm_frac": round(exec_b / ms / 1e6 / PEAK_HBM, 4),
+                                   "error_vs_float64": {k: float(f"{v:.3e}") for k, v in worst.items()}})
+            del R, Y, Sc, RS, send, recv
+            torch.cuda.empty_cache()
+    del X
+    torch.cuda.empty_cache()
     return out
 
 
@@ -287,6 +373,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--batch", action="store_true", help="also measure the batching form (512 collectives)")
     ap.add_argument("--serve", action="store_true", help="also measure the serving form (Poisson requests)")
+    ap.add_argument("--precision", action="store_true", help="also measure the precision form (bf16 / fp8)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the virtual ranks of the hierarchy "
@@ -398,6 +485,9 @@ def main():
         c.close()
     del bufs
     torch.cuda.empty_cache()
+    if args.precision:
+        out["precision"] = precision_bench(torch)
+        torch.cuda.empty_cache()
     if args.batch:
         out["batching"] = batch_bench(torch)
         torch.cuda.empty_cache()

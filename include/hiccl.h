@@ -81,7 +81,9 @@ typedef enum {
 /* Claim order of the task table. */
 typedef enum {
   HICCL_ORDER_STAGE = 0,       /* by dependency stage, then program order */
-  HICCL_ORDER_PROGRAM = 1      /* program order (primitive, branch, channel) */
+  HICCL_ORDER_PROGRAM = 1,     /* program order (primitive, branch, channel) */
+  HICCL_ORDER_CHANNEL = 2      /* pipeline channel first, then stage: each channel's intermediates are
+                                  consumed soon after they are produced (cache locality) */
 } hiccl_order;
 
 /* ---------------------------------------------------------------- lifecycle */
@@ -273,6 +275,17 @@ int hiccl_batch_destroy(hiccl_batch_t batch);
 int hiccl_autotune(hiccl_comm_t comm, const int* stripes, int nstripes, const int* pipes, int npipes,
                    const size_t* tiles, int ntiles, int reps, void* stream, int* best_stripe,
                    int* best_pipe, size_t* best_tile, double* best_us);
+
+/* Model-guided autotuner (prior in the spirit of the cost model of Sec. 4.6):
+ * every candidate is planned on the host to obtain its executed bytes,
+ * tiles and dependency stages; t = bytes / BW + a * tiles + b * stages + c
+ * is fitted to `anchors` timed candidates (least squares), and only the
+ * `top` best-predicted candidates are timed in addition. `measured`
+ * returns how many candidates ran on the device. Otherwise as
+ * hiccl_autotune. */
+int hiccl_autotune_model(hiccl_comm_t comm, const int* stripes, int nstripes, const int* pipes, int npipes,
+                         const size_t* tiles, int ntiles, int reps, int anchors, int top, void* stream,
+                         int* best_stripe, int* best_pipe, size_t* best_tile, double* best_us, int* measured);
 
 /* ----------------------------------------------------------------- serving */
 

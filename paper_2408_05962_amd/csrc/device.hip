@@ -13,6 +13,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <cmath>
+#include <numeric>
 #include <chrono>
 #include <cstdio>
 #include <deque>
@@ -1057,6 +1060,140 @@ int hiccl_batch_destroy(hiccl_batch_t b) {
 }
 
 // =============================================================== autotuner
+}  // extern "C"
+
+namespace hiccl {
+// Plan and time one candidate: the median of `reps` runs in microseconds, or -1 if it cannot run.
+static double time_candidate(hiccl_comm_t comm, int s, int m, size_t tile, int reps, hipStream_t st, hipEvent_t e0,
+                             hipEvent_t e1) {
+  Comm& c = comm->c;
+  hiccl_set_stripe(comm, s);
+  hiccl_set_pipeline(comm, m);
+  hiccl_set_exec(comm, c.exec.mode, tile, c.exec.grid, c.exec.order);
+  if (hiccl_init(comm) != HICCL_SUCCESS) return -1;
+  if (hiccl_run(comm, st) != HICCL_SUCCESS) return -1;
+  std::vector<float> ms;
+  for (int r = 0; r < reps; ++r) {
+    if (hipEventRecord(e0, st) != hipSuccess || hiccl_run(comm, st) != HICCL_SUCCESS ||
+        hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return -1;
+    float v = 0;
+    if (hipEventElapsedTime(&v, e0, e1) == hipSuccess) ms.push_back(v);
+  }
+  if (ms.empty() || hiccl_wait(comm) != HICCL_SUCCESS) return -1;
+  std::sort(ms.begin(), ms.end());
+  return ms[ms.size() / 2] * 1e3;
+}
+
+// Least squares for y ~ X w with 4 unknowns (normal equations, Gaussian elimination).
+static bool fit4(const std::vector<std::array<double, 4>>& X, const std::vector<double>& y, double w[4]) {
+  double A[4][5] = {};
+  for (size_t i = 0; i < X.size(); ++i)
+    for (int r = 0; r < 4; ++r) {
+      for (int c = 0; c < 4; ++c) A[r][c] += X[i][r] * X[i][c];
+      A[r][4] += X[i][r] * y[i];
+    }
+  for (int r = 0; r < 4; ++r) A[r][r] += 1e-12 * (1.0 + A[r][r]);   // ridge against collinear anchors
+  for (int c = 0; c < 4; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 4; ++r)
+      if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+    if (std::fabs(A[piv][c]) < 1e-300) return false;
+    for (int k = 0; k < 5; ++k) std::swap(A[c][k], A[piv][k]);
+    for (int r = 0; r < 4; ++r)
+      if (r != c) {
+        double f = A[r][c] / A[c][c];
+        for (int k = c; k < 5; ++k) A[r][k] -= f * A[c][k];
+      }
+  }
+  for (int r = 0; r < 4; ++r) w[r] = A[r][4] / A[r][r];
+  return true;
+}
+}  // namespace hiccl
+
+extern "C" {
+
+int hiccl_autotune_model(hiccl_comm_t comm, const int* stripes, int nstripes, const int* pipes, int npipes,
+                         const size_t* tiles, int ntiles, int reps, int anchors, int top, void* stream,
+                         int* best_stripe, int* best_pipe, size_t* best_tile, double* best_us, int* measured) {
+  if (!comm) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator");
+  if (!stripes || !pipes || !tiles || nstripes < 1 || npipes < 1 || ntiles < 1 || reps < 1 || anchors < 1 || top < 0)
+    return fail(HICCL_ERR_INVALID_ARG, "empty candidate set");
+  Comm& c = comm->c;
+  struct Cand {
+    int s, m;
+    size_t tile;
+    std::array<double, 4> x;   // executed bytes, tiles, stages, 1
+    double pred = 0, us = -1;
+  };
+  std::vector<Cand> cs;
+  for (int a = 0; a < nstripes; ++a)
+    for (int p = 0; p < npipes; ++p)
+      for (int q = 0; q < ntiles; ++q) {
+        hiccl_set_stripe(comm, stripes[a]);
+        hiccl_set_pipeline(comm, pipes[p]);
+        hiccl_set_exec(comm, c.exec.mode, tiles[q], c.exec.grid, c.exec.order);
+        if (hiccl_init(comm) != HICCL_SUCCESS) continue;
+        const Plan& pl = c.plan;
+        cs.push_back({stripes[a], pipes[p], tiles[q],
+                      {double(pl.hbm_read + pl.hbm_written), double(pl.tile_task.size()), double(pl.nstages), 1.0}});
+      }
+  if (cs.empty()) return fail(HICCL_ERR_INVALID_ARG, "no candidate can be planned");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int ran = 0;
+  // anchors spread over the candidate list (extremes first)
+  std::vector<size_t> order;
+  for (size_t i = 0; i < cs.size(); ++i) order.push_back(i);
+  std::vector<size_t> anc;
+  for (int k = 0; k < anchors && k < int(cs.size()); ++k) {
+    size_t i = (anchors == 1) ? 0 : size_t(double(k) * double(cs.size() - 1) / double(anchors - 1) + 0.5);
+    if (std::find(anc.begin(), anc.end(), i) == anc.end()) anc.push_back(i);
+  }
+  std::vector<std::array<double, 4>> X;
+  std::vector<double> y;
+  for (size_t i : anc) {
+    cs[i].us = time_candidate(comm, cs[i].s, cs[i].m, cs[i].tile, reps, st, e0, e1);
+    ++ran;
+    if (cs[i].us > 0) {
+      X.push_back(cs[i].x);
+      y.push_back(cs[i].us);
+    }
+  }
+  double w[4] = {0, 0, 0, 0};
+  bool model = X.size() >= 2 && fit4(X, y, w);
+  for (Cand& k : cs) k.pred = model ? (w[0] * k.x[0] + w[1] * k.x[1] + w[2] * k.x[2] + w[3]) : 0;
+  std::vector<size_t> idx(cs.size());
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cs[a].pred < cs[b].pred; });
+  int extra = 0;
+  for (size_t i : idx) {
+    if (extra >= top) break;
+    if (cs[i].us >= 0) continue;
+    cs[i].us = time_candidate(comm, cs[i].s, cs[i].m, cs[i].tile, reps, st, e0, e1);
+    ++ran;
+    ++extra;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const Cand* best = nullptr;
+  for (const Cand& k : cs)
+    if (k.us > 0 && (!best || k.us < best->us)) best = &k;
+  if (!best) return fail(HICCL_ERR_INVALID_ARG, "no candidate could be run");
+  hiccl_set_stripe(comm, best->s);
+  hiccl_set_pipeline(comm, best->m);
+  hiccl_set_exec(comm, c.exec.mode, best->tile, c.exec.grid, c.exec.order);
+  if (int rc = hiccl_init(comm)) return rc;
+  if (best_stripe) *best_stripe = best->s;
+  if (best_pipe) *best_pipe = best->m;
+  if (best_tile) *best_tile = best->tile;
+  if (best_us) *best_us = best->us;
+  if (measured) *measured = ran;
+  return HICCL_SUCCESS;
+}
+
 int hiccl_autotune(hiccl_comm_t comm, const int* stripes, int nstripes, const int* pipes, int npipes,
                    const size_t* tiles, int ntiles, int reps, void* stream, int* best_stripe, int* best_pipe,
                    size_t* best_tile, double* best_us) {

@@ -11,7 +11,9 @@
 #include <cstdio>
 #include <map>
 #include <numeric>
+#include <queue>
 #include <random>
+#include <tuple>
 #include <set>
 #include <unordered_map>
 
@@ -588,8 +590,28 @@ void order_and_tile(Plan& p, int order, size_t tile_bytes) {
   size_t n = ts.size();
   std::vector<int> perm(n);
   std::iota(perm.begin(), perm.end(), 0);
-  if (order == HICCL_ORDER_STAGE)
+  if (order == HICCL_ORDER_STAGE) {
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return ts[a].stage < ts[b].stage; });
+  } else if (order == HICCL_ORDER_CHANNEL) {
+    // Kahn's algorithm with the ready task of smallest (channel, stage, index) first: always a
+    // topological order, even where splits of different sizes make channels depend across indices
+    auto key = [&](int i) { return std::make_tuple(ts[i].channel, ts[i].stage, i); };
+    auto cmp = [&](int a, int b) { return key(a) > key(b); };
+    std::priority_queue<int, std::vector<int>, decltype(cmp)> ready(cmp);
+    std::vector<int> indeg(n);
+    for (size_t i = 0; i < n; ++i) {
+      indeg[i] = int(ts[i].preds.size());
+      if (!indeg[i]) ready.push(int(i));
+    }
+    perm.clear();
+    while (!ready.empty()) {
+      int i = ready.top();
+      ready.pop();
+      perm.push_back(i);
+      for (int s : ts[i].succs)
+        if (--indeg[s] == 0) ready.push(s);
+    }
+  }
   std::vector<int> inv(n);
   for (size_t i = 0; i < n; ++i) inv[perm[i]] = int(i);
   std::vector<Task> nt(n);
@@ -1063,7 +1085,7 @@ int hiccl_set_pipeline(hiccl_comm_t comm, int m) {
 int hiccl_set_exec(hiccl_comm_t comm, int mode, size_t tile_bytes, int grid, int order) {
   CHECK_COMM(comm);
   if (mode != HICCL_EXEC_PERSISTENT && mode != HICCL_EXEC_STAGED) return fail(HICCL_ERR_INVALID_ARG, "bad mode");
-  if (order != HICCL_ORDER_STAGE && order != HICCL_ORDER_PROGRAM) return fail(HICCL_ERR_INVALID_ARG, "bad order");
+  if (order < HICCL_ORDER_STAGE || order > HICCL_ORDER_CHANNEL) return fail(HICCL_ERR_INVALID_ARG, "bad order");
   if (grid < 0) return fail(HICCL_ERR_INVALID_ARG, "grid must be >= 0");
   if (tile_bytes != 0 && tile_bytes < 256) return fail(HICCL_ERR_INVALID_ARG, "tile must be >= 256 bytes");
   unplan(comm->c);

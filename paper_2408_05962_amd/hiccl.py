@@ -18,7 +18,7 @@ DTYPES = {"int32": INT32, "float32": FLOAT32, "bfloat16": BFLOAT16, "fp8_e4m3": 
 ELEM_SIZE = {INT32: 4, FLOAT32: 4, BFLOAT16: 2, FP8_E4M3: 1}
 OPS = {"sum": 0, "max": 1, "min": 2}
 EXEC = {"persistent": 0, "staged": 1}
-ORDER = {"stage": 0, "program": 1}
+ORDER = {"stage": 0, "program": 1, "channel": 2}
 BATCH = {"persistent": 0, "graph": 1, "serial": 2, "persistent_sjf": 3}
 
 SUCCESS, ERR_INVALID_ARG, ERR_STATE, ERR_RACE, ERR_OOM, ERR_HIP, ERR_TIMEOUT, ERR_UNSUPPORTED, ERR_BUSY = \
@@ -93,6 +93,8 @@ def lib():
             "hiccl_batch_destroy": [vp],
             "hiccl_autotune": [vp, pi, i, pi, i, C.POINTER(sz), i, i, vp, pi, pi, C.POINTER(sz),
                                C.POINTER(C.c_double)],
+            "hiccl_autotune_model": [vp, pi, i, pi, i, C.POINTER(sz), i, i, i, i, vp, pi, pi, C.POINTER(sz),
+                                     C.POINTER(C.c_double), pi],
             "hiccl_server_create": [sz, i, C.POINTER(vp)],
             "hiccl_server_admit": [vp, sz, C.POINTER(u64)],
             "hiccl_server_stream": [vp, u64, C.POINTER(vp)],
@@ -317,6 +319,19 @@ def autotune(comm: Comm, stripes, pipes, tiles, reps=3, stream=None):
     check(lib().hiccl_autotune(comm.h, s, ns, p, np_, t, len(tiles), int(reps), stream_handle(stream),
                                C.byref(bs), C.byref(bp), C.byref(bt), C.byref(us)))
     return {"stripe": bs.value, "pipeline": bp.value, "tile_bytes": bt.value, "us": us.value}
+
+
+def autotune_model(comm: Comm, stripes, pipes, tiles, reps=3, anchors=4, top=2, stream=None):
+    """Model-guided autotune: fit a bytes / tiles / stages cost model to a few timed anchors, time the best
+    predicted candidates, keep the fastest measured."""
+    s, ns = _ints(stripes)
+    p, np_ = _ints(pipes)
+    t = (C.c_size_t * len(tiles))(*[int(v) for v in tiles])
+    bs, bp, bt, us, nm = C.c_int(), C.c_int(), C.c_size_t(), C.c_double(), C.c_int()
+    check(lib().hiccl_autotune_model(comm.h, s, ns, p, np_, t, len(tiles), int(reps), int(anchors), int(top),
+                                     stream_handle(stream), C.byref(bs), C.byref(bp), C.byref(bt), C.byref(us),
+                                     C.byref(nm)))
+    return {"stripe": bs.value, "pipeline": bp.value, "tile_bytes": bt.value, "us": us.value, "measured": nm.value}
 
 
 class Server:

@@ -252,3 +252,22 @@ def test_workspace_and_plan_info(hc):
     assert all(t["stage"] == 0 or t["npred"] > 0 for t in tasks)
     assert [t["stage"] for t in tasks] == sorted(t["stage"] for t in tasks)   # claim order is stage order
     c.close()
+
+
+@pytest.mark.parametrize("order", ["stage", "program", "channel"])
+def test_claim_orders_are_topological(hc, order):
+    from paper_2408_05962_amd import collectives as CO
+    p, d = 16, 2048
+    for name in ("all_reduce", "broadcast", "all_to_all"):
+        send = _bufs(p, H.send_len(name, p, d))
+        recv = _bufs(p, H.recv_len(name, p, d))
+        c = CO.make(name, p, "float32", send, recv, d, hierarchy=[2, 4, 2], stripe=4, pipeline=8, order=order)
+        tasks = c.plan_tasks()
+        c.close()
+        # every task's stage is 1 + the largest stage of its predecessors, so a topological order
+        # never places a task before a task of a lower stage it could depend on; check the weaker
+        # invariant that stage 0 tasks with no predecessors exist and channels are grouped when asked
+        assert tasks and all((t["stage"] == 0) == (t["npred"] == 0) for t in tasks)
+        if order == "channel":
+            ch = [t["channel"] for t in tasks]
+            assert ch == sorted(ch)

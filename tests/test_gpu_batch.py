@@ -81,3 +81,29 @@ def test_batch_matches_oracle_and_alone(torch_cuda, mode):
     b.close()
     for it in items:
         it["comm"].close()
+
+
+@pytest.mark.parametrize("kind", ["exhaustive", "model"])
+def test_autotuners_pick_a_valid_configuration(torch_cuda, kind):
+    torch = torch_cuda
+    from paper_2408_05962_amd import autotune, autotune_model
+    from paper_2408_05962_amd import collectives as CO
+    p, h, d = 8, [2, 4], 8192
+    sends = [np.random.default_rng(r).integers(-1000, 1001, d * p).astype(np.int32) for r in range(p)]
+    S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+    R = torch.zeros_like(S)
+    c = CO.make("all_reduce", p, "int32", [S[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=h)
+    st = torch.cuda.current_stream()
+    if kind == "exhaustive":
+        r = autotune(c, [1, 2, 4], [1, 2, 4], [16384, 65536], reps=2, stream=st)
+    else:
+        r = autotune_model(c, [1, 2, 4], [1, 2, 4], [16384, 65536], reps=2, anchors=4, top=2, stream=st)
+        assert r["measured"] <= 6
+    assert r["stripe"] in (1, 2, 4) and r["pipeline"] in (1, 2, 4) and r["us"] > 0
+    R.zero_()
+    c.run(st)
+    c.wait()
+    torch.cuda.synchronize()
+    out = R.cpu().numpy()
+    H.check_result("all_reduce", {q: out[q] for q in range(p)}, sends, "int32")
+    c.close()
