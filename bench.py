@@ -362,13 +362,34 @@ def serve_bench(torch, ntemplates=48, nreq=400, fractions=(0.25, 0.5, 0.75, 0.9,
     return out
 
 
+def measured_traffic(mode, tile, grid):
+    """HBM bytes per launch of the headline kernel from the committed rocprofv3 counter runs
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when they were taken on another
+    kernel source or launch configuration."""
+    import hashlib
+    kname = "hiccl_staged" if mode == "staged" else "hiccl_persistent"
+    path = os.path.join(ROOT, "profiles", f"traffic_{kname}_six_collectives_16r_64MiB.json")
+    src = os.path.join(ROOT, "paper_2408_05962_amd", "csrc", "device.hip")
+    if tile or grid or not os.path.exists(path) or not os.path.exists(src):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("device_source_sha256") != sha or rec.get("mode") != mode:
+        return None
+    return round(rec["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--mode", default="persistent", choices=["persistent", "staged"])
-    ap.add_argument("--tile", type=int, default=65536)
+    ap.add_argument("--mode", default="staged", choices=["persistent", "staged"])
+    ap.add_argument("--tile", type=int, default=0, help="tile bytes (0 = the executor's default)")
+    ap.add_argument("--grid", type=int, default=0, help="workgroups (0 = the executor's default)")
+    ap.add_argument("--no-alt", action="store_true", help="skip timing the other executor")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--batch", action="store_true", help="also measure the batching form (512 collectives)")
@@ -391,50 +412,63 @@ def main():
     S_el = S_BYTES // 4
     d = S_el // P
 
-    comms, bufs, info = {}, {}, {}
+    bufs = {}
     for i, name in enumerate(SIX):
         snd = synth.device_buffers("float32", 100 + i, P, send_len(name, P, d), device="cuda")
         rcv = torch.zeros((P, recv_len(name, P, d)), dtype=torch.float32, device=dev)
-        c = CO.make(name, P, "float32", [snd[r] for r in range(P)], [rcv[r] for r in range(P)], d, hierarchy=HIER,
-                    stripe=STRIPE, pipeline=PIPE, exec_mode=args.mode, tile_bytes=args.tile)
-        comms[name] = c
         bufs[name] = (snd, rcv)
-        info[name] = c.plan_info()
     torch.cuda.synchronize()
 
-    for _ in range(args.warmup):
+    def measure(mode, tile, grid, steps, warmup):
+        """Time `steps` passes of the six collectives with one executor; per-collective HIP events on `st`."""
+        comms, info = {}, {}
         for name in SIX:
-            comms[name].run(st)
-    for name in SIX:
-        comms[name].wait()
-    torch.cuda.synchronize()
-
-    ev = {name: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                 for _ in range(args.steps)] for name in SIX}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
+            snd, rcv = bufs[name]
+            c = CO.make(name, P, "float32", [snd[r] for r in range(P)], [rcv[r] for r in range(P)], d,
+                        hierarchy=HIER, stripe=STRIPE, pipeline=PIPE, exec_mode=mode, tile_bytes=tile, grid=grid)
+            comms[name] = c
+            info[name] = c.plan_info()
+        for _ in range(warmup):
+            for name in SIX:
+                comms[name].run(st)
         for name in SIX:
-            a, b = ev[name][k]
-            a.record(st)
-            comms[name].run(st)
-            b.record(st)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for name in SIX:
-        comms[name].wait()
+            comms[name].wait()
+        torch.cuda.synchronize()
+        ev = {name: [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                     for _ in range(steps)] for name in SIX}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            for name in SIX:
+                a, b = ev[name][k]
+                a.record(st)
+                comms[name].run(st)
+                b.record(st)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for name in SIX:
+            comms[name].wait()
+            comms[name].close()
+        per, kern_ms, kern_bytes, launches = {}, 0.0, 0, 0
+        for name in SIX:
+            ms = sum(a.elapsed_time(b) for a, b in ev[name]) / steps
+            exec_bytes = info[name]["hbm_read"] + info[name]["hbm_written"]
+            nl = info[name]["nstages"] if mode == "staged" else 1
+            kern_ms += ms
+            kern_bytes += exec_bytes
+            launches += nl
+            per[name] = {"ms": round(ms, 4), "algbw_GBps": round(S_BYTES / ms / 1e6, 1),
+                         "exec_bytes": exec_bytes, "exec_GBps": round(exec_bytes / ms / 1e6, 1),
+                         "hbm_frac": round(exec_bytes / ms / 1e6 / PEAK_HBM, 4), "launches": nl,
+                         "tasks": info[name]["ntasks"], "tiles": info[name]["ntiles"],
+                         "stages": info[name]["nstages"]}
+        return {"step_ms": (t1 - t0) * 1e3 / steps, "per": per, "kern_ms": kern_ms, "kern_bytes": kern_bytes,
+                "launches": launches, "tile": tile, "grid": grid}
 
-    step_ms = (t1 - t0) * 1e3 / args.steps
-    per, kern_ms, kern_bytes = {}, 0.0, 0
-    for name in SIX:
-        ms = sum(a.elapsed_time(b) for a, b in ev[name]) / args.steps
-        exec_bytes = info[name]["hbm_read"] + info[name]["hbm_written"]
-        kern_ms += ms
-        kern_bytes += exec_bytes
-        per[name] = {"ms": round(ms, 4), "algbw_GBps": round(S_BYTES / ms / 1e6, 1),
-                     "exec_bytes": exec_bytes, "exec_GBps": round(exec_bytes / ms / 1e6, 1),
-                     "hbm_frac": round(exec_bytes / ms / 1e6 / PEAK_HBM, 4),
-                     "tasks": info[name]["ntasks"], "tiles": info[name]["ntiles"], "stages": info[name]["nstages"]}
+    head = measure(args.mode, args.tile, args.grid, args.steps, args.warmup)
+    alt_mode = "persistent" if args.mode == "staged" else "staged"
+    alt = None if args.no_alt else measure(alt_mode, 0, 0, max(5, args.steps // 2), 2)
+    step_ms, per, kern_ms, kern_bytes = head["step_ms"], head["per"], head["kern_ms"], head["kern_bytes"]
 
     # sanity: All-Reduce rows agree and match a host sum at a few sampled elements
     snd, rcv = bufs["all_reduce"]
@@ -459,6 +493,8 @@ def main():
     del x, y
 
     achieved = kern_bytes / kern_ms / 1e6
+    kname = "hiccl_staged<256, false>" if args.mode == "staged" else "hiccl_persistent<256, false>"
+    traffic = measured_traffic(args.mode, args.tile, args.grid)
     out = {
         "metric": METRIC,
         "value": round(len(SIX) * S_BYTES / step_ms / 1e6, 2),
@@ -475,14 +511,21 @@ def main():
         "config": {"workload": "six collectives (broadcast, reduce, all-gather, reduce-scatter, all-reduce, "
                                "all-to-all), 16 virtual ranks as {2,4,2}, 64 MiB float32 N(0,1) per rank, "
                                "stripe 4, pipeline 8",
-                   "executor": args.mode, "tile_bytes": args.tile},
+                   "executor": args.mode, "tile_bytes": head["tile"] or "default", "grid": head["grid"] or "default"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM, 4), "traffic": None},
+                     "frac": round(achieved / PEAK_HBM, 4), "traffic": traffic, "kernel": kname,
+                     "launches_per_step": head["launches"],
+                     "bytes_per_launch": round(kern_bytes / head["launches"]),
+                     "avg_launch_us": round(kern_ms * 1e3 / head["launches"], 2)},
         "per_collective": per,
         "empirical_copy_GBps": round(copy_gbps, 1),
     }
-    for c in comms.values():
-        c.close()
+    if alt is not None:
+        out["other_executor"] = {"executor": alt_mode, "ms_per_step": round(alt["step_ms"], 4),
+                                 "value": round(len(SIX) * S_BYTES / alt["step_ms"] / 1e6, 2),
+                                 "exec_GBps": round(alt["kern_bytes"] / alt["kern_ms"] / 1e6, 1),
+                                 "hbm_frac": round(alt["kern_bytes"] / alt["kern_ms"] / 1e6 / PEAK_HBM, 4),
+                                 "per_collective_ms": {n: v["ms"] for n, v in alt["per"].items()}}
     del bufs
     torch.cuda.empty_cache()
     if args.precision:

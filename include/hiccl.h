@@ -145,9 +145,11 @@ int hiccl_set_ring(hiccl_comm_t comm, int n);
 int hiccl_set_pipeline(hiccl_comm_t comm, int m);
 
 /* Executor launch options (not a paper parameter): form (hiccl_exec_mode),
- * tile size in bytes (work unit claimed by one workgroup; 0 = default
- * 64 KiB, rounded to whole 16-byte vectors and whole fp8 scale blocks),
- * grid (workgroups; 0 = fill the device), claim order (hiccl_order). */
+ * tile size in bytes (work unit of one workgroup; 0 = default: 64 KiB for
+ * the persistent executor, 32 KiB for stage launches; rounded to whole
+ * 16-byte vectors and whole fp8 scale blocks), grid (workgroups of the
+ * persistent launch, or of each stage launch; 0 = default: one per compute
+ * unit persistent, two per compute unit staged), claim order (hiccl_order). */
 int hiccl_set_exec(hiccl_comm_t comm, int mode, size_t tile_bytes, int grid, int order);
 
 /* ------------------------------------------------------------------ init */
@@ -180,7 +182,7 @@ int hiccl_run(hiccl_comm_t comm, void* stream);
  * reused. Returns TIMEOUT if the executor gave up a dependency wait. */
 int hiccl_wait(hiccl_comm_t comm);
 
-/* Workgroups of the next runs (0 = fill the device), without re-planning.
+/* Workgroups of the next runs (0 = the default of hiccl_set_exec), without re-planning.
  * A smaller grid lets several collectives share the device at once. */
 int hiccl_set_grid(hiccl_comm_t comm, int grid);
 

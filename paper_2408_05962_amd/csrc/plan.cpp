@@ -1090,7 +1090,8 @@ int hiccl_set_exec(hiccl_comm_t comm, int mode, size_t tile_bytes, int grid, int
   if (tile_bytes != 0 && tile_bytes < 256) return fail(HICCL_ERR_INVALID_ARG, "tile must be >= 256 bytes");
   unplan(comm->c);
   comm->c.exec.mode = mode;
-  comm->c.exec.tile_bytes = tile_bytes ? tile_bytes : 64 * 1024;
+  // default tile: 64 KiB for the persistent executor, 32 KiB for stage launches (measured best)
+  comm->c.exec.tile_bytes = tile_bytes ? tile_bytes : (mode == HICCL_EXEC_STAGED ? 32 * 1024 : 64 * 1024);
   comm->c.exec.grid = grid;
   comm->c.exec.order = order;
   return HICCL_SUCCESS;
