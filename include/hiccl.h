@@ -305,7 +305,10 @@ int hiccl_server_admit(hiccl_server_t srv, size_t footprint, uint64_t* ticket);
 /* The stream (hipStream_t) of an admitted request's slot, for the caller's
  * own preparation work before the launch. */
 int hiccl_server_stream(hiccl_server_t srv, uint64_t ticket, void** stream);
-/* Start an admitted request: enqueue `comm` (initialized) on its slot. */
+/* Start an admitted request: enqueue `comm` (initialized) on its slot. It
+ * sets the request's grid (hiccl_set_grid): the executor's full default
+ * when no other request is running, else about 3 x compute units / slots
+ * workgroups, so that concurrent requests overlap on the device. */
 int hiccl_server_launch(hiccl_server_t srv, uint64_t ticket, hiccl_comm_t comm);
 /* Retire finished requests (frees their slots and budget); non-blocking. */
 int hiccl_server_progress(hiccl_server_t srv);

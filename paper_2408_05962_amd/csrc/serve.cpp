@@ -4,6 +4,7 @@
 // and their work overlaps on the device (continuous batching).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <unordered_map>
 #include <vector>
 
@@ -24,6 +25,7 @@ struct hiccl_server_s {
   std::vector<int64_t> slot_owner;     // ticket or -1
   std::unordered_map<uint64_t, Req> reqs;
   uint64_t next = 1;
+  int share_grid = 0;                  // workgroups of a request that runs beside others
 };
 
 #define HIP_OK(expr, what)                                                         \
@@ -45,6 +47,11 @@ int hiccl_server_create(size_t hbm_budget, int slots, hiccl_server_t* out) {
   if (!out || slots < 1 || hbm_budget == 0) return fail(HICCL_ERR_INVALID_ARG, "bad server parameters");
   auto* s = new hiccl_server_s;
   s->budget = hbm_budget;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 1;
+  // concurrent requests share the device: about three workgroups per compute unit in total
+  s->share_grid = std::max(1, 3 * cus / slots);
   for (int i = 0; i < slots; ++i) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -95,6 +102,12 @@ int hiccl_server_launch(hiccl_server_t s, uint64_t ticket, hiccl_comm_t comm) {
     return fail(HICCL_ERR_STATE, "ticket is not admitted or already launched");
   auto& r = it->second;
   hipStream_t st = s->streams[r.slot];
+  // a request that starts while others run gets a share of the device; one
+  // that starts alone gets the executor's full default grid
+  if (int rc = hiccl_server_progress(s)) return rc;
+  int running = 0;
+  for (const auto& kv : s->reqs) running += kv.second.launched && !kv.second.done;
+  if (int rc = hiccl_set_grid(comm, running ? s->share_grid : 0)) return rc;
   HIP_OK(hipEventCreate(&r.start), "event");
   HIP_OK(hipEventCreate(&r.stop), "event");
   HIP_OK(hipEventRecord(r.start, st), "event record");

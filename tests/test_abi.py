@@ -209,7 +209,7 @@ def test_level_bytes_match_oracle(hc, name, h, s):
 
 @pytest.mark.parametrize("name,coef", [("broadcast", 32), ("reduce", 38.5), ("all_gather", 32),
                                        ("reduce_scatter", 38.5), ("all_reduce", 68.5), ("all_to_all", 44)])
-def test_executed_bytes_config2_shape(hc, name, coef):
+def test_executed_bytes_16_ranks_2x4x2_shape(hc, name, coef):
     """Executed device-memory bytes of the {2,4,2}, s = 4 schedules as multiples of the per-rank buffer S."""
     from paper_2408_05962_amd import collectives as CO
     p, h, s, m = 16, [2, 4, 2], 4, 8

@@ -29,7 +29,7 @@ def _host_inputs(name, p, d, dtype, seed):
 
 
 def _run(torch, name, p, h, dtype, d, s=1, m=1, mode="persistent", sends=None, seed=0, reps=1, tile=0, root=0,
-         op="sum", order="stage", ring=1):
+         op="sum", order="stage", ring=1, grid=0, claim=None):
     from paper_2408_05962_amd import collectives as CO
     if sends is None:
         sends = _host_inputs(name, p, d, dtype, seed)
@@ -39,7 +39,9 @@ def _run(torch, name, p, h, dtype, d, s=1, m=1, mode="persistent", sends=None, s
     send = [S[r] for r in range(p)]
     recv = [R[r] for r in range(p)]
     c = CO.make(name, p, dtype, send, recv, d, hierarchy=h, stripe=s, pipeline=m, exec_mode=mode, tile_bytes=tile,
-                root=root, op=op, order=order, ring=ring)
+                root=root, op=op, order=order, ring=ring, grid=grid)
+    if claim:
+        c.set_claim(*claim)
     c.set_spin_limit(1 << 20)    # a stalled dependency fails the test within seconds
     st = torch.cuda.current_stream()
     outs = []
@@ -58,7 +60,7 @@ def _got(name, out, p, root):
     return {r: out[r] for r in exp_ranks}
 
 
-def test_config1_allreduce_int32_bit_exact(torch_cuda):
+def test_allreduce_4_ranks_2x2_int32_bit_exact(torch_cuda):
     """All-Reduce over 4 ranks as {2,2}, 65,536 int32 per rank in [-1000, 1000], s = m = 1."""
     import synth
     p, n = 4, 65536
@@ -95,6 +97,19 @@ def test_staged_matches_persistent(torch_cuda, name):
     assert np.array_equal(a[0].view(np.uint32), b[0].view(np.uint32))
     assert np.array_equal(a[0].view(np.uint32), c[0].view(np.uint32))
     assert np.array_equal(a[0].view(np.uint32), e[0].view(np.uint32))
+
+
+@pytest.mark.parametrize("mode", ["persistent", "staged"])
+@pytest.mark.parametrize("grid,claim", [(1, None), (7, (8, 1)), (300, (3, 5)), (1000, (8, 16))])
+def test_launch_shapes_do_not_change_results(torch_cuda, mode, grid, claim):
+    """Grid, queue count and claim batch decide only who runs which tile, never the arithmetic."""
+    name, h, s, m, p = "all_reduce", [2, 4, 2], 4, 2, 16
+    sends, ref = _run(torch_cuda, name, p, h, "float32", 2048 + 5, s=s, m=m, seed=21, tile=4096)
+    _, got = _run(torch_cuda, name, p, h, "float32", 2048 + 5, s=s, m=m, sends=sends, tile=4096, mode=mode,
+                  grid=grid, claim=claim, reps=2)
+    for out in got:
+        assert np.array_equal(out.view(np.uint32), ref[0].view(np.uint32))
+    H.check_result(name, _got(name, ref[0], p, 0), sends, "float32", h=h, s=s)
 
 
 @pytest.mark.parametrize("op", ["max", "min"])
@@ -151,7 +166,7 @@ def test_many_reruns_stress(torch_cuda):
 
 
 @pytest.mark.parametrize("name", H.SIX)
-def test_config2_full_size(torch_cuda, name):
+def test_six_collectives_16_ranks_64MiB_full_size(torch_cuda, name):
     """Six collectives, 16 ranks as {2,4,2}, 64 MiB float32 per rank ~ N(0,1), stripe 4, pipeline 8 (bench launch)."""
     import torch
     import synth

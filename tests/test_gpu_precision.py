@@ -132,7 +132,7 @@ def test_payload_collectives_bit_exact(torch_cuda, dtype, name, h, s, m):
 
 @pytest.mark.parametrize("dtype", ["float32", "bfloat16", "fp8_e4m3"])
 @pytest.mark.parametrize("name", ["all_reduce", "reduce_scatter"])
-def test_config3_full_size_sampled(torch_cuda, dtype, name):
+def test_precision_16_ranks_2e28_elements_sampled(torch_cuda, dtype, name):
     """16 ranks as {2,4,2}, 2^28 elements per rank ~ N(0,1) with 1 % of entries x 1e3, stripe 4,
     pipeline 8: results checked on sampled 256-element blocks of every chunk against the oracle
     (order-exact), and the error against float64 reported per format."""

@@ -78,7 +78,7 @@ def test_single_step_allreduce_form():
     H.check_result("all_reduce", got, sends, "float32", order_exact=False)
 
 
-def test_config1_shape():
+def test_allreduce_4_ranks_2x2_schedule_shape():
     """All-Reduce of 4 ranks as {2,2}, 65,536 int32 per rank: 4 stages (RS node, RS top, AG top, AG leaf)."""
     import synth
     _lib()
