@@ -209,3 +209,39 @@ def test_precision_16_ranks_2e28_elements_sampled(torch_cuda, dtype, name):
     print(f"\n{name} {dtype}: error vs float64 on {len(stats)} sampled blocks: {worst}", flush=True)
     del X, R
     torch.cuda.empty_cache()
+
+
+def test_fp8_node_every_code_pair(torch_cuda):
+    """One two-operand fp8 reduction node (Reduce over 2 ranks) fed every pair of non-NaN e4m3 codes,
+    with per-block scales that vary the operands' relative magnitude: widening, summing, rescaling and
+    round-to-nearest-even encoding (ties and subnormals included) equal the oracle's node byte for byte."""
+    torch = torch_cuda
+    from paper_2408_05962_amd import collectives as CO
+    codes = np.array([c for c in range(256) if c not in (0x7F, 0xFF)], dtype=np.uint8)
+    a = np.repeat(codes, len(codes))
+    b = np.tile(codes, len(codes))
+    n = (len(a) + 255) // 256 * 256
+    n += n % 512                                   # two equal chunks of whole blocks
+    A = np.zeros(n, np.uint8)
+    B = np.zeros(n, np.uint8)
+    A[:len(a)], B[:len(b)] = a, b
+    nb = n // 256
+    sa = np.ones(nb, np.float32)
+    sb = np.exp2(np.arange(nb) % 9 - 4).astype(np.float32)     # 2^-4 .. 2^4
+    dev = lambda x: torch.from_numpy(x).to("cuda")  # noqa: E731
+    Y = [dev(A), dev(B)]
+    S = [dev(sa), dev(sb)]
+    R = [torch.zeros(n, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    RS = [torch.zeros(nb, dtype=torch.float32, device="cuda") for _ in range(2)]
+    c = CO.make("reduce", 2, "fp8_e4m3", [(Y[r], S[r]) for r in range(2)], [(R[r], RS[r]) for r in range(2)], n // 2,
+                hierarchy=[2])
+    c.set_spin_limit(1 << 20)
+    c.run(torch.cuda.current_stream())
+    c.wait()
+    torch.cuda.synchronize()
+    c.close()
+    ec, es = OQ.node_fp8([(A, sa), (B, sb)])
+    assert np.array_equal(RS[0].cpu().numpy(), es)
+    got = R[0].cpu().numpy()
+    bad = np.nonzero(got != ec)[0]
+    assert bad.size == 0, f"{bad.size} codes differ, first at {bad[:5]}: got {got[bad[:5]]} want {ec[bad[:5]]}"
