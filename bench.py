@@ -149,7 +149,7 @@ def batch_bench(torch, n=512, seed=4, reps=3):
     out = {"collectives": n, "ranks": BATCH_P, "hierarchy": BATCH_H, "sum_S_bytes": total_S,
            "sum_exec_bytes": total_exec, "tune_s": round(t_tune, 2), "plan_s": round(t_plan, 2),
            "tuned": {f"{k[0]}/{SIZE_CLASSES[k[1]][0]}": v for k, v in table.items()}}
-    for mode in ("serial", "graph", "persistent", "persistent_sjf"):
+    for mode in ("serial", "graph", "persistent", "persistent_sjf", "staged"):
         b = Batch(comms, mode)
         b.run(st)
         b.wait()

@@ -255,7 +255,9 @@ typedef enum {
   HICCL_BATCH_PERSISTENT = 0,  /* all task tables merged into one persistent launch */
   HICCL_BATCH_GRAPH = 1,       /* one launch per collective, captured once into a hipGraph and replayed */
   HICCL_BATCH_SERIAL = 2,      /* one launch per collective on the stream (reference form) */
-  HICCL_BATCH_PERSISTENT_SJF = 3  /* one merged launch, smallest collectives claimed first */
+  HICCL_BATCH_PERSISTENT_SJF = 3, /* one merged launch, smallest collectives claimed first */
+  HICCL_BATCH_STAGED = 4          /* task tables merged by dependency stage; one launch per stage for
+                                     all collectives together (completion = end of a collective's last stage) */
 } hiccl_batch_mode;
 
 /* Group initialized communicators (any mix of dtypes and hierarchies) into

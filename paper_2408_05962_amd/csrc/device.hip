@@ -119,7 +119,7 @@ __device__ __forceinline__ int scale_exp(float amax) {
 }
 
 // ------------------------------------------------------------ tile kernels
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 8;     // 16-byte vectors in flight per lane and operand
 
 // Data path. Every operand byte is read and written with buffer
 // instructions that carry the streaming (nt) and device-coherent (sc1)
@@ -181,7 +181,15 @@ __device__ __forceinline__ void copy_bytes(uint64_t s, uint64_t d, uint64_t nb) 
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) st16(rd, (i + u * BLOCK) * 16u, r[u]);
     }
-    for (; i < nv; i += BLOCK) st16(rd, i * 16u, ld16(rs, i * 16u));
+    if (i < nv) {   // the last (at most kUnroll - 1) vectors of this lane, loads still all in flight
+      uint4 r[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (i + u * BLOCK < nv) r[u] = ld16(rs, (i + u * BLOCK) * 16u);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+        if (i + u * BLOCK < nv) st16(rd, (i + u * BLOCK) * 16u, r[u]);
+    }
     for (uint32_t b = (nv << 4) + tid; b < nb; b += BLOCK) st1(rd, b, ld1(rs, b));
   } else if (((s | d) & 3u) == 0) {
     const uint32_t nw = uint32_t(nb >> 2);
@@ -250,6 +258,24 @@ __device__ __forceinline__ void reduce32(const DevTask* t, int k, uint64_t e0, u
           for (int j = 1; j < (K ? K : 1); ++j) acc = op32v<FLT, OP>(acc, v[j][u]);
           st16(rd, (i + u * BLOCK) * 16u, acc);
         }
+      }
+      if (i < nv) {   // predicated last pass: every remaining load of this lane in flight together
+        uint4 v[K ? K : 1][kUnroll];
+#pragma unroll
+        for (int j = 0; j < (K ? K : 1); ++j)
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u)
+            if (i + u * BLOCK < nv) v[j][u] = ld16(rs[j], (i + u * BLOCK) * 16u);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (i + u * BLOCK < nv) {
+            uint4 acc = v[0][u];
+#pragma unroll
+            for (int j = 1; j < (K ? K : 1); ++j) acc = op32v<FLT, OP>(acc, v[j][u]);
+            st16(rd, (i + u * BLOCK) * 16u, acc);
+          }
+        }
+        i = nv;
       }
     } else {
       for (; i + (kUnroll - 1) * BLOCK < nv; i += kUnroll * BLOCK) {
@@ -863,7 +889,8 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
   std::vector<Ref> refs;
   for (uint32_t p = 0; p < plans.size(); ++p)
     for (uint32_t i = 0; i < plans[p]->tasks.size(); ++i) refs.push_back({p, i});
-  if (plans.size() > 1 && merge == 0) {
+  // stage launches need the table grouped by stage, whatever each plan's claim order
+  if ((plans.size() > 1 && merge == 0) || mode == HICCL_EXEC_STAGED) {
     std::stable_sort(refs.begin(), refs.end(), [&](const Ref& x, const Ref& y) {
       return plans[x.plan]->tasks[x.idx].stage < plans[y.plan]->tasks[y.idx].stage;
     });
@@ -963,6 +990,20 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
   return 0;
 }
 
+// One stage launch over tiles [lo, hi) of a staged table.
+static int launch_stage(const Exe& ex, hipStream_t st, uint32_t lo, uint32_t hi) {
+  if (hi <= lo) return 0;
+  ExecArgs a = ex.args();
+  const uint32_t want = uint32_t(stage_grid(ex.stage_grid));
+  int g = int(std::min<uint32_t>(hi - lo, want));
+  if (ex.narrow)
+    hipLaunchKernelGGL((hiccl_staged<kBlock, true>), dim3(g), dim3(kBlock), 0, st, a, lo, hi);
+  else
+    hipLaunchKernelGGL((hiccl_staged<kBlock, false>), dim3(g), dim3(kBlock), 0, st, a, lo, hi);
+  HIP_TRY(hipGetLastError());
+  return 0;
+}
+
 static int launch(const Exe& ex, hipStream_t st) {
   if (ex.ntiles == 0) return 0;
   ExecArgs a = ex.args();
@@ -972,16 +1013,8 @@ static int launch(const Exe& ex, hipStream_t st) {
     else
       hipLaunchKernelGGL((hiccl_persistent<kBlock, false>), dim3(ex.grid), dim3(kBlock + 64), 0, st, a);
   } else {
-    for (size_t s = 0; s + 1 < ex.stage_tile_begin.size(); ++s) {
-      uint32_t lo = ex.stage_tile_begin[s], hi = ex.stage_tile_begin[s + 1];
-      if (hi <= lo) continue;
-      const uint32_t want = uint32_t(stage_grid(ex.stage_grid));
-      int g = int(std::min<uint32_t>(hi - lo, want));
-      if (ex.narrow)
-        hipLaunchKernelGGL((hiccl_staged<kBlock, true>), dim3(g), dim3(kBlock), 0, st, a, lo, hi);
-      else
-        hipLaunchKernelGGL((hiccl_staged<kBlock, false>), dim3(g), dim3(kBlock), 0, st, a, lo, hi);
-    }
+    for (size_t s = 0; s + 1 < ex.stage_tile_begin.size(); ++s)
+      if (int rc = launch_stage(ex, st, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1])) return rc;
   }
   HIP_TRY(hipGetLastError());
   return 0;
@@ -1090,6 +1123,8 @@ struct hiccl_batch_s {
   hipEvent_t ev = nullptr;
   bool launched = false;
   double clock_hz = 1e8;
+  std::vector<hipEvent_t> stage_ev;      // staged form: start, then the end of every stage launch
+  std::vector<int> last_stage;           // staged form: each collective's last stage
 };
 
 namespace hiccl {
@@ -1106,6 +1141,18 @@ static int batch_prepare(hiccl_batch_s* b) {
     if (int rc = upload(plans, wsb, HICCL_EXEC_PERSISTENT, x.grid, x.spin_limit, true, b->merged, x.queues, x.batch,
                         b->mode == HICCL_BATCH_PERSISTENT_SJF ? 1 : 0))
       return rc;
+  } else if (b->mode == HICCL_BATCH_STAGED) {
+    // stage s of every collective depends only on its own earlier stages, so
+    // one launch per merged stage keeps every collective's order
+    if (int rc = upload(plans, wsb, HICCL_EXEC_STAGED, 0, x.spin_limit, false, b->merged, x.queues, x.batch, 0))
+      return rc;
+    for (const Plan* pl : plans) {
+      int last = 0;
+      for (const Task& t : pl->tasks) last = std::max(last, t.stage);
+      b->last_stage.push_back(last);
+    }
+    b->stage_ev.resize(b->merged.stage_tile_begin.size());
+    for (hipEvent_t& e : b->stage_ev) HIP_TRY(hipEventCreate(&e));
   } else {
     b->each.resize(plans.size());
     for (size_t i = 0; i < plans.size(); ++i) {
@@ -1127,7 +1174,7 @@ extern "C" {
 
 int hiccl_batch_create(const hiccl_comm_t* comms, int n, int mode, hiccl_batch_t* out) {
   if (!comms || n < 1 || !out) return fail(HICCL_ERR_INVALID_ARG, "batch needs at least one communicator");
-  if (mode < HICCL_BATCH_PERSISTENT || mode > HICCL_BATCH_PERSISTENT_SJF)
+  if (mode < HICCL_BATCH_PERSISTENT || mode > HICCL_BATCH_STAGED)
     return fail(HICCL_ERR_INVALID_ARG, "bad batch mode");
   for (int i = 0; i < n; ++i) {
     if (!comms[i]) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator in batch");
@@ -1149,6 +1196,13 @@ int hiccl_batch_run(hiccl_batch_t b, void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (b->mode == HICCL_BATCH_PERSISTENT || b->mode == HICCL_BATCH_PERSISTENT_SJF) {
     if (int rc = launch(b->merged, st)) return rc;
+  } else if (b->mode == HICCL_BATCH_STAGED) {
+    const Exe& ex = b->merged;
+    HIP_TRY(hipEventRecord(b->stage_ev[0], st));
+    for (size_t s = 0; s + 1 < ex.stage_tile_begin.size(); ++s) {
+      if (int rc = launch_stage(ex, st, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1])) return rc;
+      HIP_TRY(hipEventRecord(b->stage_ev[s + 1], st));
+    }
   } else if (b->mode == HICCL_BATCH_SERIAL) {
     for (const Exe& e : b->each)
       if (int rc = launch(e, st)) return rc;
@@ -1196,6 +1250,16 @@ int hiccl_batch_wait(hiccl_batch_t b) {
 int hiccl_batch_times(hiccl_batch_t b, uint64_t* ns, int n) {
   if (!b || !ns || n != int(b->comms.size())) return fail(HICCL_ERR_INVALID_ARG, "bad batch times request");
   std::vector<unsigned long long> stamp(n), start;
+  if (b->mode == HICCL_BATCH_STAGED) {
+    if (!b->launched) return fail(HICCL_ERR_STATE, "batch has not run");
+    HIP_TRY(hipEventSynchronize(b->ev));
+    for (int i = 0; i < n; ++i) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, b->stage_ev[0], b->stage_ev[size_t(b->last_stage[i]) + 1]));
+      ns[i] = uint64_t(double(ms) * 1e6);
+    }
+    return HICCL_SUCCESS;
+  }
   if (b->mode == HICCL_BATCH_PERSISTENT || b->mode == HICCL_BATCH_PERSISTENT_SJF) {
     std::vector<unsigned long long> t(n + 1);
     HIP_TRY(hipMemcpy(t.data(), b->merged.d_times, (n + 1) * sizeof(unsigned long long), hipMemcpyDeviceToHost));
@@ -1220,6 +1284,7 @@ int hiccl_batch_destroy(hiccl_batch_t b) {
   if (b->launched) (void)hipEventSynchronize(b->ev);
   b->merged.free_all();
   for (Exe& e : b->each) e.free_all();
+  for (hipEvent_t e : b->stage_ev) (void)hipEventDestroy(e);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);

@@ -52,7 +52,7 @@ def _got(it, p=8):
     return {r: out[r] for r in ranks}
 
 
-@pytest.mark.parametrize("mode", ["persistent", "graph", "serial", "persistent_sjf"])
+@pytest.mark.parametrize("mode", ["persistent", "graph", "serial", "persistent_sjf", "staged"])
 def test_batch_matches_oracle_and_alone(torch_cuda, mode):
     torch = torch_cuda
     from paper_2408_05962_amd import Batch
@@ -107,3 +107,43 @@ def test_autotuners_pick_a_valid_configuration(torch_cuda, kind):
     out = R.cpu().numpy()
     H.check_result("all_reduce", {q: out[q] for q in range(p)}, sends, "int32")
     c.close()
+
+
+def test_staged_batch_of_program_ordered_plans(torch_cuda):
+    """The merged stage-by-stage batch regroups tables by stage even when a plan was ordered otherwise."""
+    torch = torch_cuda
+    from paper_2408_05962_amd import Batch
+    from paper_2408_05962_amd import collectives as CO
+    p, h, d = 8, [2, 4], 1000
+    outs = []
+    for mode in (None, "staged"):
+        comms, Rs, sends_all = [], [], []
+        for i, name in enumerate(["all_reduce", "broadcast", "all_to_all"]):
+            sends = [np.random.default_rng(10 * i + r).standard_normal(H.send_len(name, p, d)).astype(np.float32)
+                     for r in range(p)]
+            S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+            R = torch.zeros((p, H.recv_len(name, p, d)), dtype=torch.float32, device="cuda")
+            c = CO.make(name, p, "float32", [S[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=h,
+                        stripe=2, pipeline=2, tile_bytes=4096, order="program")
+            comms.append((c, S))
+            Rs.append(R)
+            sends_all.append((name, sends))
+        st = torch.cuda.current_stream()
+        if mode is None:
+            for c, _ in comms:
+                c.run(st)
+                c.wait()
+        else:
+            b = Batch([c for c, _ in comms], mode)
+            b.run(st)
+            b.wait()
+            b.close()
+        torch.cuda.synchronize()
+        outs.append([R.cpu().numpy() for R in Rs])
+        for (name, sends), R in zip(sends_all, outs[-1]):
+            ranks = range(p)
+            H.check_result(name, {r: R[r] for r in ranks}, sends, "float32", h=h, s=2)
+        for c, _ in comms:
+            c.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
