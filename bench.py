@@ -237,19 +237,22 @@ def precision_bench(torch, reps=5, n=1 << 28, sample_blocks=64):
                 RS = torch.zeros((p, rl // 256), dtype=torch.float32, device="cuda")
                 send = [(Y[r], Sc[r]) for r in range(p)]
                 recv = [(R[r], RS[r]) for r in range(p)]
-            c = CO.make(name, p, dtype, send, recv, d, hierarchy=h, stripe=s, pipeline=m)
-            info = c.plan_info()
-            c.run(st)
-            c.wait()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(st)
-            for _ in range(reps):
+            times = {}
+            for mode in ("staged", "persistent"):
+                c = CO.make(name, p, dtype, send, recv, d, hierarchy=h, stripe=s, pipeline=m, exec_mode=mode)
+                info = c.plan_info()
                 c.run(st)
-            e1.record(st)
-            c.wait()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            c.close()
+                c.wait()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+                for _ in range(reps):
+                    c.run(st)
+                e1.record(st)
+                c.wait()
+                torch.cuda.synchronize()
+                times[mode] = e0.elapsed_time(e1) / reps
+                c.close()
+            ms = times["staged"]
             # errors on sampled blocks: the library widens the result rows to float32 on the device;
             # the exact value is the float64 sum of the original float32 inputs
             errs = []
@@ -273,8 +276,9 @@ def precision_bench(torch, reps=5, n=1 << 28, sample_blocks=64):
             del W
             worst = {k: max(e[k] for e in errs) for k in errs[0]}
             exec_b = info["hbm_read"] + info["hbm_written"]
-            _progress(f"precision {name} {dtype}: {ms:.3f} ms")
+            _progress(f"precision {name} {dtype}: staged {ms:.3f} ms, persistent {times['persistent']:.3f} ms")
             out["results"].append({"collective": name, "payload": dtype, "ms": round(ms, 3),
+                                   "ms_persistent": round(times["persistent"], 3),
                                    "algbw_GBps": round(n * 4 / ms / 1e6, 1),
                                    "exec_bytes": exec_b, "exec_GBps": round(exec_b / ms / 1e6, 1),
                                    "hbm_frac": round(exec_b / ms / 1e6 / PEAK_HBM, 4),

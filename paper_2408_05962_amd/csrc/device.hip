@@ -390,7 +390,7 @@ __device__ __forceinline__ void reduce_fp8(const DevTask* t, int k, uint64_t e0,
 // float32 order and RNE narrowing as reduce_bf16.
 template <int BLOCK, int K>
 __device__ __forceinline__ void reduce_bf16_k(const DevTask* t, uint64_t e0, uint64_t n) {
-  constexpr int U = K >= 4 ? 2 : 4;
+  constexpr int U = K >= 4 ? 4 : 8;             // 16-byte vectors per lane and operand in flight
   const uint32_t tid = threadIdx.x;
   const uint64_t nb = n * 2;
   const uint64_t d = t->dst + e0 * 2;
@@ -453,7 +453,7 @@ __device__ __forceinline__ void reduce_bf16_k(const DevTask* t, uint64_t e0, uin
 }
 
 // fp8 payload with K (2..4) operands known at compile time: all K code
-// vectors and block scales of two 256-element blocks per lane group are
+// vectors and block scales of U 256-element blocks per lane group are
 // loaded before the arithmetic starts. Same dequantize / sum / rescale /
 // encode steps as reduce_fp8, with gfx950's packed OCP e4m3 conversions:
 // decoding is exact, and encoding rounds to nearest even; after rescaling
@@ -462,7 +462,7 @@ __device__ __forceinline__ void reduce_bf16_k(const DevTask* t, uint64_t e0, uin
 // software codec.
 template <int BLOCK, int K>
 __device__ __forceinline__ void reduce_fp8_k(const DevTask* t, uint64_t e0, uint64_t n) {
-  constexpr int U = 2;
+  constexpr int U = 8;                           // vectors per lane in flight (measured best)
   const uint32_t tid = threadIdx.x;
   const rsrc_t rd = rsrc(t->dst + e0, n);
   const rsrc_t rdsc = rsrc(t->dst_sc + (e0 / 256) * 4, (n / 256) * 4);
