@@ -84,7 +84,7 @@ def _size_class(nbytes):
     return len(SIZE_CLASSES) - 1
 
 
-def _mk(torch, CO, name, p, h, dtype, per_rank_bytes, seed, s=1, m=1, tile=0, grid=0, ring=1):
+def _mk(torch, CO, name, p, h, dtype, per_rank_bytes, seed, s=1, m=1, tile=0, grid=0, ring=1, mode="persistent"):
     """A communicator with its own device buffers for a collective of `per_rank_bytes` (largest buffer)."""
     import synth
     es = 2 if dtype == "bfloat16" else 4
@@ -97,7 +97,7 @@ def _mk(torch, CO, name, p, h, dtype, per_rank_bytes, seed, s=1, m=1, tile=0, gr
         snd = snd.to(torch.bfloat16).view(torch.int16)
     rcv = torch.zeros((p, recv_len(name, p, d)), dtype=snd.dtype, device="cuda")
     c = CO.make(name, p, dtype, [snd[r] for r in range(p)], [rcv[r] for r in range(p)], d, hierarchy=h, stripe=s,
-                pipeline=m, tile_bytes=tile, grid=grid, ring=ring)
+                pipeline=m, tile_bytes=tile, grid=grid, ring=ring, exec_mode=mode)
     return c, snd, rcv, d * p * es
 
 
@@ -295,7 +295,7 @@ SERVE_HIERS = [[2, 4], [2, 4, 2], [4, 4]]
 
 
 def serve_bench(torch, ntemplates=48, nreq=400, fractions=(0.25, 0.5, 0.75, 0.9, 1.2), slots=4,
-                budget=200 * 10 ** 9, seed=8):
+                budget=200 * 10 ** 9, seed=8, mode="persistent"):
     """Poisson stream of collective requests over resident request templates.
 
     Templates are drawn from the serving mix (type uniform over the six, hierarchy from {2x4, 2x4x2, 4x4},
@@ -317,8 +317,9 @@ def serve_bench(torch, ntemplates=48, nreq=400, fractions=(0.25, 0.5, 0.75, 0.9,
         dtype = ["int32", "float32", "bfloat16"][int(rng.integers(0, 3))]
         s = 4 if p == 16 else 2
         m = 8 if sizes[i] >= (1 << 20) else 1
-        c, snd, rcv, S = _mk(torch, CO, name, p, h, dtype, sizes[i], 7000 + i, s, m, 65536)
-        c.set_claim(1, 4)    # one tile queue: progress holds however many of its workgroups are resident
+        c, snd, rcv, S = _mk(torch, CO, name, p, h, dtype, sizes[i], 7000 + i, s, m, mode=mode)
+        if mode == "persistent":
+            c.set_claim(1, 4)    # one tile queue: progress holds however many of its workgroups are resident
         foot = snd.numel() * snd.element_size() + rcv.numel() * rcv.element_size() + c.workspace_size()
         c.run(torch.cuda.current_stream())
         c.wait()
@@ -371,7 +372,7 @@ def serve_bench(torch, ntemplates=48, nreq=400, fractions=(0.25, 0.5, 0.75, 0.9,
     span, _ = run_stream(np.zeros(nreq), picks, slots)
     mu = nreq / span
     _progress(f"serve closed loop: {mu:.1f} requests/s")
-    out = {"templates": ntemplates, "requests_per_rate": nreq, "slots": slots, "budget_bytes": budget,
+    out = {"executor": mode, "templates": ntemplates, "requests_per_rate": nreq, "slots": slots, "budget_bytes": budget,
            "mu_req_per_s": round(mu, 1), "rates": []}
     for f in fractions:
         lam = f * mu
@@ -422,6 +423,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--batch", action="store_true", help="also measure the batching form (512 collectives)")
     ap.add_argument("--serve", action="store_true", help="also measure the serving form (Poisson requests)")
+    ap.add_argument("--serve-exec", default="persistent", choices=["staged", "persistent"],
+                    help="executor of the serving templates")
     ap.add_argument("--precision", action="store_true", help="also measure the precision form (bf16 / fp8)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -564,7 +567,7 @@ def main():
         out["batching"] = batch_bench(torch)
         torch.cuda.empty_cache()
     if args.serve:
-        out["serving"] = serve_bench(torch)
+        out["serving"] = serve_bench(torch, mode=args.serve_exec)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
