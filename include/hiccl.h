@@ -146,8 +146,9 @@ int hiccl_set_pipeline(hiccl_comm_t comm, int m);
 
 /* Executor launch options (not a paper parameter): form (hiccl_exec_mode),
  * tile size in bytes (work unit of one workgroup; 0 = default: 64 KiB for
- * the persistent executor, 32 KiB for stage launches; rounded to whole
- * 16-byte vectors and whole fp8 scale blocks), grid (workgroups of the
+ * the persistent executor, 32 KiB for stage launches; at most 1 GiB;
+ * rounded to whole 16-byte vectors and whole fp8 scale blocks; hiccl_init
+ * returns INVALID_ARG if a plan would need 2^31 tiles or more), grid (workgroups of the
  * persistent launch, or of each stage launch; 0 = default: one per compute
  * unit persistent, two per compute unit staged), claim order (hiccl_order). */
 int hiccl_set_exec(hiccl_comm_t comm, int mode, size_t tile_bytes, int grid, int order);
@@ -266,9 +267,11 @@ typedef enum {
 int hiccl_batch_create(const hiccl_comm_t* comms, int n, int mode, hiccl_batch_t* out);
 int hiccl_batch_run(hiccl_batch_t batch, void* stream);
 int hiccl_batch_wait(hiccl_batch_t batch);
-/* Device completion times (ns, from the device clock, relative to the
- * batch start) of each collective of the last run: the moment its last
- * task retired. `ns` has n entries. */
+/* Completion times (ns, relative to the batch start) of each collective of
+ * the last run. Persistent forms: the device clock at the moment its last
+ * task retired. Graph / serial: the device clock when its own launch
+ * finished. Staged: stream events, the end of its last stage launch. `ns`
+ * has n entries. */
 int hiccl_batch_times(hiccl_batch_t batch, uint64_t* ns, int n);
 int hiccl_batch_destroy(hiccl_batch_t batch);
 

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <cmath>
 #include <numeric>
@@ -858,14 +859,16 @@ void device_state_free(DeviceState* s) {
 // addresses in flight and add counter traffic without adding bandwidth);
 // the stage launches are fastest with two workgroups per compute unit.
 static int cu_count() {
-  static int cached = 0;
-  if (!cached) {
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 1;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
-    cached = std::max(1, cus);
-  }
-  return cached;
+  constexpr int kMaxDevices = 64;
+  static std::atomic<int> cached[kMaxDevices];   // per device: compute units (0 = not yet asked)
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  if (dev >= 0 && dev < kMaxDevices && cached[dev].load(std::memory_order_relaxed))
+    return cached[dev].load(std::memory_order_relaxed);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1;
+  cus = std::max(1, cus);
+  if (dev >= 0 && dev < kMaxDevices) cached[dev].store(cus, std::memory_order_relaxed);
+  return cus;
 }
 static int device_grid(int want) { return want > 0 ? want : cu_count(); }
 static int stage_grid(int want) { return want > 0 ? want : 2 * cu_count(); }

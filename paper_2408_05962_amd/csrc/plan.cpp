@@ -680,6 +680,14 @@ int build_plan(Comm& c) {
   int rc = factorize_all(c, pl.tasks, ws);
   if (rc) return rc;
   build_edges(pl.tasks, pl.nedges);
+  // tile indices are 32-bit on the device
+  uint64_t tiles = 0;
+  for (const Task& t : pl.tasks) {
+    const uint64_t te = tile_elems_for(c.exec.tile_bytes, t.dtype);
+    tiles += std::max<uint64_t>(1, (t.count + te - 1) / te);
+  }
+  if (tiles >= (uint64_t(1) << 31))
+    return fail(HICCL_ERR_INVALID_ARG, "the plan would need 2^31 or more tiles: use a larger tile size");
   int order = c.exec.mode == HICCL_EXEC_STAGED ? HICCL_ORDER_STAGE : c.exec.order;
   order_and_tile(pl, order, c.exec.tile_bytes);
   pl.ws_bytes = ws;
@@ -1087,7 +1095,8 @@ int hiccl_set_exec(hiccl_comm_t comm, int mode, size_t tile_bytes, int grid, int
   if (mode != HICCL_EXEC_PERSISTENT && mode != HICCL_EXEC_STAGED) return fail(HICCL_ERR_INVALID_ARG, "bad mode");
   if (order < HICCL_ORDER_STAGE || order > HICCL_ORDER_CHANNEL) return fail(HICCL_ERR_INVALID_ARG, "bad order");
   if (grid < 0) return fail(HICCL_ERR_INVALID_ARG, "grid must be >= 0");
-  if (tile_bytes != 0 && tile_bytes < 256) return fail(HICCL_ERR_INVALID_ARG, "tile must be >= 256 bytes");
+  if (tile_bytes != 0 && (tile_bytes < 256 || tile_bytes > (size_t(1) << 30)))
+    return fail(HICCL_ERR_INVALID_ARG, "tile must be 256 bytes .. 1 GiB");   // device offsets are 32-bit
   unplan(comm->c);
   comm->c.exec.mode = mode;
   // default tile: 64 KiB for the persistent executor, 32 KiB for stage launches (measured best)

@@ -271,3 +271,19 @@ def test_claim_orders_are_topological(hc, order):
         if order == "channel":
             ch = [t["channel"] for t in tasks]
             assert ch == sorted(ch)
+
+
+def test_tile_limits(hc):
+    """Device tile offsets are 32-bit and tile indices 31-bit: out-of-range tiles are argument errors."""
+    c = hc.Comm(2, "float32")
+    assert _code(c.set_exec, "persistent", 128) == hc.ERR_INVALID_ARG
+    assert _code(c.set_exec, "persistent", (1 << 30) + 16) == hc.ERR_INVALID_ARG
+    c.set_exec("staged", 1 << 30)
+    # 2^32 elements per rank in 256-byte tiles would need 2^26 tiles per hop: fine; 2^39 bytes would not be
+    c.add_multicast([1 << 40, 1 << 41], [1 << 42, 1 << 43], 1 << 37, 0, [1])
+    c.set_exec("persistent", 256)
+    assert _code(c.init) == hc.ERR_INVALID_ARG
+    c.set_exec("persistent", 1 << 20)
+    c.init()
+    assert c.plan_info()["ntiles"] == (1 << 39) // (1 << 20)
+    c.close()
