@@ -82,8 +82,12 @@ typedef enum {
 typedef enum {
   HICCL_ORDER_STAGE = 0,       /* by dependency stage, then program order */
   HICCL_ORDER_PROGRAM = 1,     /* program order (primitive, branch, channel) */
-  HICCL_ORDER_CHANNEL = 2      /* pipeline channel first, then stage: each channel's intermediates are
+  HICCL_ORDER_CHANNEL = 2,     /* pipeline channel first, then stage: each channel's intermediates are
                                   consumed soon after they are produced (cache locality) */
+  HICCL_ORDER_CRITICAL = 3     /* by dependency stage, then longest chain of successors first: the
+                                  schedule of the step counts of Sec. 4.6 when every rank has one
+                                  link; on one GPU it separates hops that read one source, so the
+                                  stage order (which keeps them together) is the default */
 } hiccl_order;
 
 /* ---------------------------------------------------------------- lifecycle */
@@ -270,8 +274,8 @@ int hiccl_batch_wait(hiccl_batch_t batch);
 /* Completion times (ns, relative to the batch start) of each collective of
  * the last run. Persistent forms: the device clock at the moment its last
  * task retired. Graph / serial: the device clock when its own launch
- * finished. Staged: stream events, the end of its last stage launch. `ns`
- * has n entries. */
+ * finished (UNSUPPORTED if a member runs on the staged executor). Staged:
+ * stream events, the end of its last stage launch. `ns` has n entries. */
 int hiccl_batch_times(hiccl_batch_t batch, uint64_t* ns, int n);
 int hiccl_batch_destroy(hiccl_batch_t batch);
 

@@ -1269,6 +1269,9 @@ int hiccl_batch_times(hiccl_batch_t b, uint64_t* ns, int n) {
     for (int i = 0; i < n; ++i) stamp[i] = t[i];
     start.push_back(t[n]);
   } else {
+    for (int i = 0; i < n; ++i)
+      if (b->each[i].mode != HICCL_EXEC_PERSISTENT)
+        return fail(HICCL_ERR_UNSUPPORTED, "graph / serial batch times need every member on the persistent executor");
     for (int i = 0; i < n; ++i) {
       unsigned long long t[2];
       HIP_TRY(hipMemcpy(t, b->each[i].d_times, sizeof(t), hipMemcpyDeviceToHost));

@@ -592,6 +592,19 @@ void order_and_tile(Plan& p, int order, size_t tile_bytes) {
   std::iota(perm.begin(), perm.end(), 0);
   if (order == HICCL_ORDER_STAGE) {
     std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return ts[a].stage < ts[b].stage; });
+  } else if (order == HICCL_ORDER_CRITICAL) {
+    // within a stage, the task with the longest chain of successors first
+    // (critical path first): a hop that feeds deeper subtrees starts
+    // earlier, which is the schedule behind the tree and ring step counts of
+    // Sec. 4.6. Edges run from lower to higher index, so one backward pass
+    // computes every height.
+    std::vector<int> height(n, 1);
+    for (size_t i = n; i-- > 0;)
+      for (int s : ts[i].succs) height[i] = std::max(height[i], height[s] + 1);
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+      if (ts[a].stage != ts[b].stage) return ts[a].stage < ts[b].stage;
+      return height[a] > height[b];
+    });
   } else if (order == HICCL_ORDER_CHANNEL) {
     // Kahn's algorithm with the ready task of smallest (channel, stage, index) first: always a
     // topological order, even where splits of different sizes make channels depend across indices
@@ -1093,7 +1106,7 @@ int hiccl_set_pipeline(hiccl_comm_t comm, int m) {
 int hiccl_set_exec(hiccl_comm_t comm, int mode, size_t tile_bytes, int grid, int order) {
   CHECK_COMM(comm);
   if (mode != HICCL_EXEC_PERSISTENT && mode != HICCL_EXEC_STAGED) return fail(HICCL_ERR_INVALID_ARG, "bad mode");
-  if (order < HICCL_ORDER_STAGE || order > HICCL_ORDER_CHANNEL) return fail(HICCL_ERR_INVALID_ARG, "bad order");
+  if (order < HICCL_ORDER_STAGE || order > HICCL_ORDER_CRITICAL) return fail(HICCL_ERR_INVALID_ARG, "bad order");
   if (grid < 0) return fail(HICCL_ERR_INVALID_ARG, "grid must be >= 0");
   if (tile_bytes != 0 && (tile_bytes < 256 || tile_bytes > (size_t(1) << 30)))
     return fail(HICCL_ERR_INVALID_ARG, "tile must be 256 bytes .. 1 GiB");   // device offsets are 32-bit

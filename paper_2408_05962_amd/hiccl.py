@@ -18,7 +18,7 @@ DTYPES = {"int32": INT32, "float32": FLOAT32, "bfloat16": BFLOAT16, "fp8_e4m3": 
 ELEM_SIZE = {INT32: 4, FLOAT32: 4, BFLOAT16: 2, FP8_E4M3: 1}
 OPS = {"sum": 0, "max": 1, "min": 2}
 EXEC = {"persistent": 0, "staged": 1}
-ORDER = {"stage": 0, "program": 1, "channel": 2}
+ORDER = {"stage": 0, "program": 1, "channel": 2, "critical": 3}
 BATCH = {"persistent": 0, "graph": 1, "serial": 2, "persistent_sjf": 3, "staged": 4}
 
 SUCCESS, ERR_INVALID_ARG, ERR_STATE, ERR_RACE, ERR_OOM, ERR_HIP, ERR_TIMEOUT, ERR_UNSUPPORTED, ERR_BUSY = \

@@ -254,7 +254,7 @@ def test_workspace_and_plan_info(hc):
     c.close()
 
 
-@pytest.mark.parametrize("order", ["stage", "program", "channel"])
+@pytest.mark.parametrize("order", ["stage", "program", "channel", "critical"])
 def test_claim_orders_are_topological(hc, order):
     from paper_2408_05962_amd import collectives as CO
     p, d = 16, 2048
@@ -271,6 +271,10 @@ def test_claim_orders_are_topological(hc, order):
         if order == "channel":
             ch = [t["channel"] for t in tasks]
             assert ch == sorted(ch)
+        if order in ("stage", "critical"):
+            # a predecessor always has a lower stage, so stage-sorted tables are topological
+            st = [t["stage"] for t in tasks]
+            assert st == sorted(st)
 
 
 def test_tile_limits(hc):

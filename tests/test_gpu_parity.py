@@ -94,6 +94,9 @@ def test_staged_matches_persistent(torch_cuda, name):
                 order="program")
     _, e = _run(torch_cuda, name, p, h, "float32", 4096, s=s, m=m, sends=sends, mode="persistent", tile=8192,
                 order="channel")
+    _, f = _run(torch_cuda, name, p, h, "float32", 4096, s=s, m=m, sends=sends, mode="persistent", tile=8192,
+                order="critical")
+    assert np.array_equal(a[0].view(np.uint32), f[0].view(np.uint32))
     assert np.array_equal(a[0].view(np.uint32), b[0].view(np.uint32))
     assert np.array_equal(a[0].view(np.uint32), c[0].view(np.uint32))
     assert np.array_equal(a[0].view(np.uint32), e[0].view(np.uint32))
