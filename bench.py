@@ -36,7 +36,7 @@ def send_len(name, p, d):
 
 def recv_len(name, p, d):
     return {"broadcast": d * p, "reduce": d * p, "all_gather": d * p, "reduce_scatter": d, "all_reduce": d * p,
-            "all_to_all": d * p}[name]
+            "all_to_all": d * p, "scatter": d, "gather": d * p}[name]
 
 
 def cpu_baseline(budget_s: float = 20.0) -> dict:
@@ -174,6 +174,113 @@ def batch_bench(torch, n=512, seed=4, reps=3):
                      "latency_us_p99": round(float(np.percentile(L, 99)), 1)}
     for c in comms:
         c.close()
+    return out
+
+
+def _time_comm(torch, c, reps=10, warm=2):
+    """Median-free mean time (ms) of `reps` back-to-back runs of one communicator, HIP events on the stream."""
+    st = torch.cuda.current_stream()
+    for _ in range(warm):
+        c.run(st)
+    c.wait()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        c.run(st)
+    e1.record(st)
+    c.wait()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def sweep_bench(torch):
+    """Measurements beside the headline: pipeline depth, ring vs tree, Scatter / Gather, and the small
+    All-Reduce's latency."""
+    import numpy as np
+
+    import synth
+    from paper_2408_05962_amd import collectives as CO
+    out = {}
+    st = torch.cuda.current_stream()
+    d = S_BYTES // 4 // P
+
+    def mk(name, h, s, m, mode, ring=1, seed=1, p=P, dd=d, dtype="float32"):
+        kind = "int32" if dtype == "int32" else "float32"
+        snd = synth.device_buffers(kind, seed, p, send_len(name, p, dd))
+        rcv = torch.zeros((p, recv_len(name, p, dd)), dtype=snd.dtype, device="cuda")
+        c = CO.make(name, p, dtype, [snd[r] for r in range(p)], [rcv[r] for r in range(p)], dd, hierarchy=h,
+                    stripe=s, pipeline=m, exec_mode=mode, ring=ring)
+        return c, snd, rcv
+
+    # pipeline depth (the shape of the paper's pipeline-depth experiment, Sec. 6.4, on HBM)
+    rows = []
+    for m in (1, 2, 4, 8, 16, 32):
+        row = {"pipeline": m}
+        for mode in ("staged", "persistent"):
+            c, snd, rcv = mk("all_reduce", HIER, STRIPE, m, mode)
+            ms = _time_comm(torch, c)
+            info = c.plan_info()
+            row[mode] = {"ms": round(ms, 4), "exec_GBps": round((info["hbm_read"] + info["hbm_written"]) / ms / 1e6, 1),
+                         "stages": info["nstages"], "tasks": info["ntasks"]}
+            c.close()
+            del snd, rcv
+        rows.append(row)
+        _progress(f"pipeline sweep m={m}: {row}")
+    out["pipeline_depth_all_reduce"] = rows
+
+    # ring(4) + tree vs tree on 16 ranks as {4,4} (Sec. 4.4)
+    ring = {}
+    for name in SIX:
+        r = {}
+        for label, rg in (("tree", 1), ("ring4", 4)):
+            for mode in ("staged", "persistent"):
+                c, snd, rcv = mk(name, [4, 4], 1, PIPE, mode, ring=rg)
+                ms = _time_comm(torch, c)
+                info = c.plan_info()
+                r[f"{label}_{mode}_ms"] = round(ms, 4)
+                r[f"{label}_stages"] = info["nstages"]
+                c.close()
+                del snd, rcv
+        ring[name] = r
+        _progress(f"ring {name}: {r}")
+    out["ring_vs_tree_16r_4x4_64MiB"] = ring
+
+    # Scatter / Gather at the headline shape
+    sg = {}
+    for name in ("scatter", "gather"):
+        c, snd, rcv = mk(name, HIER, STRIPE, PIPE, "staged")
+        ms = _time_comm(torch, c)
+        info = c.plan_info()
+        sg[name] = {"ms": round(ms, 4), "algbw_GBps": round(S_BYTES / ms / 1e6, 1),
+                    "exec_GBps": round((info["hbm_read"] + info["hbm_written"]) / ms / 1e6, 1)}
+        c.close()
+        del snd, rcv
+    out["scatter_gather"] = sg
+    _progress(f"scatter/gather: {sg}")
+
+    # the small All-Reduce: 4 ranks as {2,2}, 65,536 int32 per rank, s = m = 1 (latency-bound)
+    small = {}
+    for mode in ("staged", "persistent"):
+        c, snd, rcv = mk("all_reduce", [2, 2], 1, 1, mode, p=4, dd=65536 // 4, dtype="int32")
+        lat = []
+        for _ in range(3):
+            c.run(st)
+        c.wait()
+        for _ in range(50):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            c.run(st)
+            e1.record(st)
+            torch.cuda.synchronize()
+            lat.append(e0.elapsed_time(e1) * 1e3)
+        c.wait()
+        ok = bool(torch.equal(rcv[0], snd.sum(0, dtype=torch.int32)) and torch.equal(rcv[3], rcv[0]))
+        small[mode] = {"latency_us_p50": round(float(np.percentile(lat, 50)), 2),
+                       "latency_us_p99": round(float(np.percentile(lat, 99)), 2), "matches_sum": ok}
+        c.close()
+        del snd, rcv
+    out["small_all_reduce_4r_2x2_int32_256KiB"] = small
+    _progress(f"small all-reduce: {small}")
     return out
 
 
@@ -426,6 +533,8 @@ def main():
     ap.add_argument("--serve-exec", default="persistent", choices=["staged", "persistent"],
                     help="executor of the serving templates")
     ap.add_argument("--precision", action="store_true", help="also measure the precision form (bf16 / fp8)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also measure pipeline depth, ring vs tree, Scatter / Gather and the small All-Reduce")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the virtual ranks of the hierarchy "
@@ -562,6 +671,9 @@ def main():
     torch.cuda.empty_cache()
     if args.precision:
         out["precision"] = precision_bench(torch)
+        torch.cuda.empty_cache()
+    if args.sweep:
+        out["sweep"] = sweep_bench(torch)
         torch.cuda.empty_cache()
     if args.batch:
         out["batching"] = batch_bench(torch)

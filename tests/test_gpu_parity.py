@@ -202,3 +202,80 @@ def test_ring_collectives(torch_cuda, name, h, ring, s, m):
                            seed=zlib.crc32(f"ring{name}{h}{dtype}".encode()) % 1000)
         for out in outs:
             H.check_result(name, _got(name, out, p, 0), sends, dtype, h=h, s=s, ring=ring)
+
+
+def _random_program(rng, p, L, nsteps, slot):
+    """Steps of random multicasts / reductions over sparse leaf sets. Step k reads buffer X_k and writes
+    Y_k (alternating "a" / "b"), each primitive into its own slot of Y, so no step has a race."""
+    from oracle import steps as OS
+    steps = []
+    for k in range(nsteps):
+        X, Y = ("a", "b") if k % 2 == 0 else ("b", "a")
+        prims = []
+        for q in range(L // slot):
+            n = int(rng.integers(1, slot + 1))                      # ragged counts
+            so = int(rng.integers(0, L - n + 1))                    # any read offset
+            wo = q * slot + int(rng.integers(0, slot - n + 1))      # inside this primitive's slot
+            k_leaves = int(rng.integers(1, p + 1))
+            leaves = sorted(int(x) for x in rng.choice(p, k_leaves, replace=False))
+            root = int(rng.integers(0, p))
+            send = {r: (f"{X}{r}", so) for r in range(p)}
+            recv = {r: (f"{Y}{r}", wo) for r in range(p)}
+            if rng.random() < 0.5:
+                prims.append(OS.multicast(root, leaves, n, send, recv))
+            else:
+                prims.append(OS.reduction(leaves, root, n, send, recv))
+        steps.append(prims)
+    return steps
+
+
+@pytest.mark.parametrize("p,h,s,m,ring,seed", [(12, [2, 2, 3], 3, 2, 1, 1), (12, [2, 2, 3], 2, 3, 1, 2),
+                                              (8, [2, 4], 2, 2, 2, 3), (16, [4, 4], 4, 1, 4, 4),
+                                              (8, [8], 1, 4, 1, 5)])
+@pytest.mark.parametrize("mode", ["persistent", "staged"])
+def test_random_sparse_leaf_programs(torch_cuda, p, h, s, m, ring, seed, mode):
+    """Custom collectives: multicasts and reductions over random leaf subsets and roots, ragged counts,
+    several fenced steps, against the oracle's step interpreter (int32, bit-exact)."""
+    torch = torch_cuda
+    from oracle import steps as OS
+    from paper_2408_05962_amd import Comm
+    rng = np.random.default_rng(seed)
+    L, slot = 4096, 512
+    steps = _random_program(rng, p, L, 3, slot)
+    A0 = rng.integers(-1000, 1001, (p, L)).astype(np.int32)
+    B0 = rng.integers(-1000, 1001, (p, L)).astype(np.int32)
+    A, B = torch.from_numpy(A0).to("cuda"), torch.from_numpy(B0).to("cuda")
+    base = {"a": A, "b": B}
+
+    def addr(ref):
+        name, off = ref
+        return base[name[0]][int(name[1:])].data_ptr() + off * 4
+
+    c = Comm(p, "int32")
+    for k, step in enumerate(steps):
+        if k:
+            c.add_fence()
+        for pr in step:
+            send = [addr(pr.send[r]) for r in range(p)]
+            recv = [addr(pr.recv[r]) for r in range(p)]
+            if pr.kind == "M":
+                c.add_multicast(send, recv, pr.count, pr.root, pr.leaves)
+            else:
+                c.add_reduction(send, recv, pr.count, pr.leaves, pr.root, "sum")
+    c.set_hierarchy(h)
+    c.set_stripe(s)
+    c.set_ring(ring)
+    c.set_pipeline(m)
+    c.set_exec(mode, 1024)
+    c.set_spin_limit(1 << 20)
+    c.init()
+    c.run(torch.cuda.current_stream())
+    c.wait()
+    torch.cuda.synchronize()
+    c.close()
+    mem = OS.Memory({**{f"a{r}": A0[r] for r in range(p)}, **{f"b{r}": B0[r] for r in range(p)}})
+    OS.run(mem, steps)
+    gotA, gotB = A.cpu().numpy(), B.cpu().numpy()
+    for r in range(p):
+        assert np.array_equal(gotA[r], mem.result(f"a{r}", np.int32)), f"rank {r} buffer a"
+        assert np.array_equal(gotB[r], mem.result(f"b{r}", np.int32)), f"rank {r} buffer b"

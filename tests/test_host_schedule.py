@@ -184,3 +184,50 @@ def test_two_step_compositions(name, dtype, h, s, m):
         else:
             assert np.max(np.abs(recvs[r] - y) / np.maximum(1, np.abs(y))) < 1e-5, (name, r)
         assert np.allclose(mem.result(f"y{r}", np.float64 if dtype == "float32" else np.int32), y)
+
+
+@pytest.mark.parametrize("p,h,s,m,ring,seed", [(12, [2, 2, 3], 3, 2, 1, 1), (12, [2, 2, 3], 2, 3, 1, 2),
+                                              (8, [2, 4], 2, 2, 2, 3), (16, [4, 4], 4, 1, 4, 4),
+                                              (8, [8], 1, 4, 1, 5)])
+def test_random_sparse_leaf_programs_host(p, h, s, m, ring, seed):
+    """The GPU parity programs of random sparse-leaf primitives, run by the host schedule checker in
+    random dependency orders, against the oracle's step interpreter."""
+    from oracle import steps as OS
+    from paper_2408_05962_amd import Comm
+    from tests.test_gpu_parity import _random_program
+    rng = np.random.default_rng(seed)
+    L, slot = 4096, 512
+    steps = _random_program(rng, p, L, 3, slot)
+    A0 = rng.integers(-1000, 1001, (p, L)).astype(np.int32)
+    B0 = rng.integers(-1000, 1001, (p, L)).astype(np.int32)
+    A, B = A0.copy(), B0.copy()
+    base = {"a": A, "b": B}
+
+    def addr(ref):
+        name, off = ref
+        return base[name[0]][int(name[1:])].ctypes.data + off * 4
+
+    c = Comm(p, "int32")
+    for k, step in enumerate(steps):
+        if k:
+            c.add_fence()
+        for pr in step:
+            send = [addr(pr.send[r]) for r in range(p)]
+            recv = [addr(pr.recv[r]) for r in range(p)]
+            if pr.kind == "M":
+                c.add_multicast(send, recv, pr.count, pr.root, pr.leaves)
+            else:
+                c.add_reduction(send, recv, pr.count, pr.leaves, pr.root, "sum")
+    c.set_hierarchy(h)
+    c.set_stripe(s)
+    c.set_ring(ring)
+    c.set_pipeline(m)
+    c.set_exec("persistent", 1024)
+    c.init()
+    c.validate_host(seed=seed, norders=3)
+    c.close()
+    mem = OS.Memory({**{f"a{r}": A0[r] for r in range(p)}, **{f"b{r}": B0[r] for r in range(p)}})
+    OS.run(mem, steps)
+    for r in range(p):
+        assert np.array_equal(A[r], mem.result(f"a{r}", np.int32)), f"rank {r} buffer a"
+        assert np.array_equal(B[r], mem.result(f"b{r}", np.int32)), f"rank {r} buffer b"
