@@ -845,6 +845,10 @@ struct DeviceState {
   bool launched = false;
 };
 
+void device_state_set_spin_limit(DeviceState* s, uint32_t polls) {
+  if (s) s->exe.spin_limit = polls;
+}
+
 void device_state_free(DeviceState* s) {
   if (!s) return;
   s->exe.free_all();

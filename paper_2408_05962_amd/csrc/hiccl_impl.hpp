@@ -118,6 +118,7 @@ struct ExecCfg {
 
 struct DeviceState;              // device.hip
 void device_state_free(DeviceState*);
+void device_state_set_spin_limit(DeviceState*, uint32_t polls);   // takes effect on the next run
 
 struct Comm {
   int P = 1;

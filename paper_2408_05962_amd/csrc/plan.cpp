@@ -1136,10 +1136,7 @@ int hiccl_set_spin_limit(hiccl_comm_t comm, uint32_t polls) {
   CHECK_COMM(comm);
   if (polls == 0) return fail(HICCL_ERR_INVALID_ARG, "spin limit must be >= 1");
   comm->c.exec.spin_limit = polls;
-  if (comm->c.dev) {
-    device_state_free(comm->c.dev);
-    comm->c.dev = nullptr;
-  }
+  device_state_set_spin_limit(comm->c.dev, polls);   // uploaded tables and counters stay
   return HICCL_SUCCESS;
 }
 

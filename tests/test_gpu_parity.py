@@ -279,3 +279,39 @@ def test_random_sparse_leaf_programs(torch_cuda, p, h, s, m, ring, seed, mode):
     for r in range(p):
         assert np.array_equal(gotA[r], mem.result(f"a{r}", np.int32)), f"rank {r} buffer a"
         assert np.array_equal(gotB[r], mem.result(f"b{r}", np.int32)), f"rank {r} buffer b"
+
+
+def test_spin_limit_abort_is_clean_and_recoverable(torch_cuda):
+    """A spin limit of one poll makes the persistent executor give up its first unmet dependency wait:
+    the run ends (every workgroup exits), hiccl_wait reports TIMEOUT, and the same communicator then
+    runs correctly with the normal limit (the last workgroup out reset every counter)."""
+    torch = torch_cuda
+    from paper_2408_05962_amd import collectives as CO
+    from paper_2408_05962_amd.hiccl import ERR_TIMEOUT, HicclError
+    name, p, h, d = "all_reduce", 16, [2, 4, 2], 4096
+    sends = _host_inputs(name, p, d, "int32", 77)
+    S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+    R = torch.zeros((p, H.recv_len(name, p, d)), dtype=torch.int32, device="cuda")
+    c = CO.make(name, p, "int32", [S[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=h, stripe=4,
+                pipeline=2, tile_bytes=1024)
+    st = torch.cuda.current_stream()
+    c.set_spin_limit(1)
+    timeouts = 0
+    for _ in range(3):
+        c.run(st)
+        try:
+            c.wait()
+        except HicclError as e:
+            assert e.code == ERR_TIMEOUT
+            timeouts += 1
+        torch.cuda.synchronize()
+    assert timeouts > 0
+    c.set_spin_limit(1 << 20)
+    for _ in range(2):
+        R.zero_()
+        c.run(st)
+        c.wait()
+        torch.cuda.synchronize()
+        out = R.cpu().numpy()
+        H.check_result(name, {r: out[r] for r in range(p)}, sends, "int32")
+    c.close()
