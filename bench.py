@@ -119,6 +119,48 @@ def tune_table(torch, seed=9):
     return table
 
 
+def batch_policy(torch, table, n=128, seed=99):
+    """Batch-level tuning: on a batch drawn like the measured one but from another seed, time the merged
+    persistent launch with the per-class table and with the defaults (s = m = 1, default tile), and
+    return the faster policy ("table" or "defaults") with both times."""
+    import synth
+    from paper_2408_05962_amd import Batch
+    from paper_2408_05962_amd import collectives as CO
+    rng = synth.choice_stream(seed, 2)
+    sizes = synth.log_uniform_sizes(seed, n, 4 << 10, 64 << 20, BATCH_P * 16)
+    st = torch.cuda.current_stream()
+    bufs, times = [], {}
+    for i in range(n):
+        name = SIX[int(rng.integers(0, 6))]
+        dtype = "int32" if rng.random() < 0.5 else "float32"
+        c, snd, rcv, S = _mk(torch, CO, name, BATCH_P, BATCH_H, dtype, sizes[i], 9000 + i)
+        c.close()
+        bufs.append((name, dtype, snd, rcv, S // (BATCH_P * 4), _size_class(sizes[i])))
+    for policy in ("table", "defaults"):
+        comms = []
+        for name, dtype, snd, rcv, d, cls in bufs:
+            s, m, tile = table[(name, cls)] if policy == "table" else (1, 1, 0)
+            comms.append(CO.make(name, BATCH_P, dtype, [snd[r] for r in range(BATCH_P)],
+                                 [rcv[r] for r in range(BATCH_P)], d, hierarchy=BATCH_H, stripe=s, pipeline=m,
+                                 tile_bytes=tile))
+        b = Batch(comms, "persistent")
+        b.run(st)
+        b.wait()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(3):
+            b.run(st)
+        e1.record(st)
+        b.wait()
+        torch.cuda.synchronize()
+        times[policy] = round(e0.elapsed_time(e1) / 3, 3)
+        b.close()
+        for c in comms:
+            c.close()
+    del bufs
+    return min(times, key=times.get), times
+
+
 def batch_bench(torch, n=512, seed=4, reps=3):
     import numpy as np
 
@@ -127,6 +169,8 @@ def batch_bench(torch, n=512, seed=4, reps=3):
     from paper_2408_05962_amd import collectives as CO
     t_tune = time.perf_counter()
     table = tune_table(torch)
+    policy, policy_ms = batch_policy(torch, table)
+    _progress(f"batch policy: {policy} {policy_ms}")
     t_tune = time.perf_counter() - t_tune
     rng = synth.choice_stream(seed, 2)
     sizes = synth.log_uniform_sizes(seed, n, 4 << 10, 64 << 20, BATCH_P * 16)
@@ -135,10 +179,10 @@ def batch_bench(torch, n=512, seed=4, reps=3):
     for i in range(n):
         name = SIX[int(rng.integers(0, 6))]
         dtype = "int32" if rng.random() < 0.5 else "float32"
-        s, m, tile = table[(name, _size_class(sizes[i]))]
+        s, m, tile = table[(name, _size_class(sizes[i]))] if policy == "table" else (1, 1, 0)
         c, snd, rcv, S = _mk(torch, CO, name, BATCH_P, BATCH_H, dtype, sizes[i], 5000 + i, s, m, tile)
         info = c.plan_info()
-        items.append((c, snd, rcv, S, info["hbm_read"] + info["hbm_written"]))
+        items.append((c, snd, rcv, S, info["hbm_read"] + info["hbm_written"], name, dtype))
         if (i + 1) % 128 == 0:
             _progress(f"batch: planned {i + 1} of {n}")
     t_plan = time.perf_counter() - t_plan
@@ -148,8 +192,9 @@ def batch_bench(torch, n=512, seed=4, reps=3):
     st = torch.cuda.current_stream()
     out = {"collectives": n, "ranks": BATCH_P, "hierarchy": BATCH_H, "sum_S_bytes": total_S,
            "sum_exec_bytes": total_exec, "tune_s": round(t_tune, 2), "plan_s": round(t_plan, 2),
-           "tuned": {f"{k[0]}/{SIZE_CLASSES[k[1]][0]}": v for k, v in table.items()}}
-    for mode in ("serial", "graph", "persistent", "persistent_sjf", "staged"):
+           "tuned": {f"{k[0]}/{SIZE_CLASSES[k[1]][0]}": v for k, v in table.items()},
+           "policy": policy, "policy_tuning_ms": policy_ms}
+    def timed(comms, mode, total_exec):
         b = Batch(comms, mode)
         b.run(st)
         b.wait()
@@ -165,20 +210,40 @@ def batch_bench(torch, n=512, seed=4, reps=3):
             lat.append(np.asarray(b.times_ns(), dtype=np.float64) / 1e3)
         b.close()
         ms = float(np.median(spans))
-        _progress(f"batch {mode}: {ms:.3f} ms")
         L = np.concatenate(lat)
-        out[mode] = {"makespan_ms": round(ms, 3), "algbw_GBps": round(total_S / ms / 1e6, 1),
-                     "exec_GBps": round(total_exec / ms / 1e6, 1),
-                     "hbm_frac": round(total_exec / ms / 1e6 / PEAK_HBM, 4),
-                     "latency_us_p50": round(float(np.percentile(L, 50)), 1),
-                     "latency_us_p99": round(float(np.percentile(L, 99)), 1)}
+        return {"makespan_ms": round(ms, 3), "algbw_GBps": round(total_S / ms / 1e6, 1),
+                "exec_GBps": round(total_exec / ms / 1e6, 1),
+                "hbm_frac": round(total_exec / ms / 1e6 / PEAK_HBM, 4),
+                "latency_us_p50": round(float(np.percentile(L, 50)), 1),
+                "latency_us_p99": round(float(np.percentile(L, 99)), 1)}
+
+    for mode in ("serial", "graph", "persistent", "persistent_sjf", "staged"):
+        out[mode] = timed(comms, mode, total_exec)
+        _progress(f"batch {mode}: {out[mode]['makespan_ms']:.3f} ms")
     for c in comms:
+        c.close()
+    # the same collectives on the same buffers under the policy not chosen: what the choice is worth
+    other = "defaults" if policy == "table" else "table"
+    plain = []
+    for i, (c, snd, rcv, S, _, name, dtype) in enumerate(items):
+        d = S // (BATCH_P * 4)
+        s, m, tile = table[(name, _size_class(sizes[i]))] if other == "table" else (1, 1, 0)
+        plain.append(CO.make(name, BATCH_P, dtype, [snd[r] for r in range(BATCH_P)], [rcv[r] for r in range(BATCH_P)],
+                             d, hierarchy=BATCH_H, stripe=s, pipeline=m, tile_bytes=tile))
+    plain_exec = 0
+    for c in plain:
+        info = c.plan_info()
+        plain_exec += info["hbm_read"] + info["hbm_written"]
+    for mode in ("serial", "persistent"):
+        out[f"{other}_{mode}"] = timed(plain, mode, plain_exec)
+        _progress(f"batch {other} {mode}: {out[f'{other}_{mode}']['makespan_ms']:.3f} ms")
+    for c in plain:
         c.close()
     return out
 
 
 def _time_comm(torch, c, reps=10, warm=2):
-    """Median-free mean time (ms) of `reps` back-to-back runs of one communicator, HIP events on the stream."""
+    """Mean time (ms) of `reps` back-to-back runs of one communicator, HIP events on the stream."""
     st = torch.cuda.current_stream()
     for _ in range(warm):
         c.run(st)
