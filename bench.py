@@ -593,7 +593,9 @@ def main():
     ap.add_argument("--no-alt", action="store_true", help="skip timing the other executor")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
-    ap.add_argument("--batch", action="store_true", help="also measure the batching form (512 collectives)")
+    ap.add_argument("--batch", action="store_true", help="(default) measure the batching form: 512 collectives, "
+                    "batched vs one launch per collective, throughput and p50/p99 latency")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batching form")
     ap.add_argument("--serve", action="store_true", help="also measure the serving form (Poisson requests)")
     ap.add_argument("--serve-exec", default="persistent", choices=["staged", "persistent"],
                     help="executor of the serving templates")
@@ -740,7 +742,7 @@ def main():
     if args.sweep:
         out["sweep"] = sweep_bench(torch)
         torch.cuda.empty_cache()
-    if args.batch:
+    if not args.no_batch:
         out["batching"] = batch_bench(torch)
         torch.cuda.empty_cache()
     if args.serve:

@@ -2,7 +2,7 @@
 // kernels (16-byte vector copy; fused k-operand elementwise reduce for
 // int32 / float32 / bf16 / fp8-with-scales), the persistent executor whose
 // dependency progress lives in device counters, the one-launch-per-stage
-// form, batching, the autotuner, the serving loop and payload conversions.
+// form, batching, the autotuners and payload conversions.
 //
 // Method: HiCCL (arXiv 2408.05962). A stage of Sec. 4.5 is a set of
 // point-to-point transfers optionally followed by a reduction computation;
@@ -17,12 +17,7 @@
 #include <array>
 #include <cmath>
 #include <numeric>
-#include <chrono>
 #include <cstdio>
-#include <deque>
-#include <map>
-#include <mutex>
-#include <unordered_map>
 
 #include "hiccl_impl.hpp"
 
