@@ -196,12 +196,20 @@ __device__ __forceinline__ void copy_bytes(uint64_t s, uint64_t d, uint64_t nb) 
   }
 }
 
+// Descriptor fields are the same for every lane of a wave; reading them
+// through readfirstlane keeps them in scalar registers whether the
+// descriptor sits in global memory or in an LDS slot.
+__device__ __forceinline__ uint32_t uni32(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+  return (uint64_t(uni32(uint32_t(x >> 32))) << 32) | uni32(uint32_t(x));
+}
+
 // Operand j's data address (element 0 of the task).
 __device__ __forceinline__ uint64_t src_addr(const DevTask* t, int j, int k) {
-  return k <= 4 ? t->src[j] : reinterpret_cast<const uint64_t*>(t->src[0])[j];
+  return uni64(k <= 4 ? t->src[j] : reinterpret_cast<const uint64_t*>(uni64(t->src[0]))[j]);
 }
 __device__ __forceinline__ uint64_t src_sc_addr(const DevTask* t, int j, int k) {
-  return k <= 4 ? t->src_sc[j] : reinterpret_cast<const uint64_t*>(t->src_sc[0])[j];
+  return uni64(k <= 4 ? t->src_sc[j] : reinterpret_cast<const uint64_t*>(uni64(t->src_sc[0]))[j]);
 }
 
 // 32-bit lanes: float32 or int32 (two's complement wrap) with sum / max / min.
@@ -230,7 +238,7 @@ __device__ __forceinline__ void reduce32(const DevTask* t, int k, uint64_t e0, u
   const uint32_t tid = threadIdx.x;
   const int kk = K ? K : k;
   const uint64_t nb = n * 4;
-  const uint64_t d = t->dst + e0 * 4;
+  const uint64_t d = uni64(t->dst) + e0 * 4;
   const rsrc_t rd = rsrc(d, nb);
   bool vec = (d & 15u) == 0;
   for (int j = 0; j < kk; ++j) vec = vec && ((src_addr(t, j, kk) + e0 * 4) & 15u) == 0;
@@ -309,7 +317,7 @@ template <int BLOCK>
 __device__ __forceinline__ void reduce_bf16(const DevTask* t, int k, uint64_t e0, uint64_t n) {
   const uint32_t tid = threadIdx.x;
   const uint64_t nb = n * 2;
-  const uint64_t d = t->dst + e0 * 2;
+  const uint64_t d = uni64(t->dst) + e0 * 2;
   const rsrc_t rd = rsrc(d, nb);
   bool vec = (d & 15u) == 0;
   for (int j = 0; j < k; ++j) vec = vec && ((src_addr(t, j, k) + e0 * 2) & 15u) == 0;
@@ -343,8 +351,8 @@ __device__ __forceinline__ void reduce_bf16(const DevTask* t, int k, uint64_t e0
 template <int BLOCK>
 __device__ __forceinline__ void reduce_fp8(const DevTask* t, int k, uint64_t e0, uint64_t n) {
   const uint32_t tid = threadIdx.x;
-  const rsrc_t rd = rsrc(t->dst + e0, n);
-  const rsrc_t rdsc = rsrc(t->dst_sc + (e0 / 256) * 4, (n / 256) * 4);
+  const rsrc_t rd = rsrc(uni64(t->dst) + e0, n);
+  const rsrc_t rdsc = rsrc(uni64(t->dst_sc) + (e0 / 256) * 4, (n / 256) * 4);
   const uint32_t nv = uint32_t(n >> 4);          // 16-code vectors
   const uint32_t nv_round = (nv + BLOCK - 1) / BLOCK * BLOCK;
   for (uint32_t i = tid; i < nv_round; i += BLOCK) {
@@ -389,7 +397,7 @@ __device__ __forceinline__ void reduce_bf16_k(const DevTask* t, uint64_t e0, uin
   constexpr int U = K >= 4 ? 4 : 8;             // 16-byte vectors per lane and operand in flight
   const uint32_t tid = threadIdx.x;
   const uint64_t nb = n * 2;
-  const uint64_t d = t->dst + e0 * 2;
+  const uint64_t d = uni64(t->dst) + e0 * 2;
   const rsrc_t rd = rsrc(d, nb);
   rsrc_t rs[K];
   bool vec = (d & 15u) == 0;
@@ -460,8 +468,8 @@ template <int BLOCK, int K>
 __device__ __forceinline__ void reduce_fp8_k(const DevTask* t, uint64_t e0, uint64_t n) {
   constexpr int U = 8;                           // vectors per lane in flight (measured best)
   const uint32_t tid = threadIdx.x;
-  const rsrc_t rd = rsrc(t->dst + e0, n);
-  const rsrc_t rdsc = rsrc(t->dst_sc + (e0 / 256) * 4, (n / 256) * 4);
+  const rsrc_t rd = rsrc(uni64(t->dst) + e0, n);
+  const rsrc_t rdsc = rsrc(uni64(t->dst_sc) + (e0 / 256) * 4, (n / 256) * 4);
   rsrc_t rs[K], rsc[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
@@ -533,16 +541,17 @@ __device__ __forceinline__ void reduce_fp8_k(const DevTask* t, uint64_t e0, uint
 // int32 / float32 executor higher.
 template <int BLOCK, bool NARROW>
 __device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t tile) {
-  const uint32_t meta = t->meta;
+  const uint32_t meta = uni32(t->meta);
   const int kind = meta & 3, op = (meta >> 2) & 3, dt = (meta >> 4) & 15, k = int(meta >> 8);
-  const uint64_t e0 = uint64_t(tile - t->first_tile) * t->tile_elems;
-  const uint64_t e1 = min(e0 + t->tile_elems, t->count);
+  const uint64_t te = uni64(t->tile_elems);
+  const uint64_t e0 = uint64_t(tile - uni32(t->first_tile)) * te;
+  const uint64_t e1 = min(e0 + te, uni64(t->count));
   const uint64_t n = e1 - e0;
   if (kind == kCopy) {
     const uint64_t es = dt == HICCL_BFLOAT16 ? 2 : (dt == HICCL_FP8_E4M3 ? 1 : 4);
-    copy_bytes<BLOCK>(t->src[0] + e0 * es, t->dst + e0 * es, n * es);
+    copy_bytes<BLOCK>(uni64(t->src[0]) + e0 * es, uni64(t->dst) + e0 * es, n * es);
     if (NARROW && dt == HICCL_FP8_E4M3)
-      copy_bytes<BLOCK>(t->src_sc[0] + (e0 / 256) * 4, t->dst_sc + (e0 / 256) * 4, (n / 256) * 4);
+      copy_bytes<BLOCK>(uni64(t->src_sc[0]) + (e0 / 256) * 4, uni64(t->dst_sc) + (e0 / 256) * 4, (n / 256) * 4);
     return;
   }
   if (dt == HICCL_FLOAT32) {
@@ -589,22 +598,31 @@ __device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t
 
 __device__ __forceinline__ unsigned long long dev_clock() { return wall_clock64(); }
 
-// Retire one tile of task `k`: the last tile of the task releases its
-// successors and, when the task is its collective's last, stamps the
-// completion time. The tile's data stores are device-coherent and complete
-// (every worker wave waited before the workgroup barrier that precedes this
-// call), so counting it is the release.
-__device__ __forceinline__ void retire(const ExecArgs& a, const DevTask* t, uint32_t k) {
-  if (t->ntiles > 1) {
-    uint32_t old = __hip_atomic_fetch_add(&a.done[k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old + 1 != t->ntiles) return;
+// Retire-side fields of a claimed tile's task, read from the task's
+// descriptor when the tile is posted and kept in the scheduler lane's
+// registers until the tile retires.
+struct TileRef {
+  uint32_t k, nsucc, succ_begin, ntiles, comm;
+};
+
+// Retire one tile: the last tile of its task releases the task's successors
+// and, when the task is its collective's last, stamps the completion time.
+// A task that releases nothing (no successors, no stamp) needs no counter
+// traffic at all. The tile's data stores are device-coherent and complete
+// (every worker wave that ran it waited before the workgroup barrier that
+// precedes this call), so counting it is the release.
+__device__ __forceinline__ void retire(const ExecArgs& a, const TileRef& r) {
+  if (!r.nsucc && !a.times) return;
+  if (r.ntiles > 1) {
+    uint32_t old = __hip_atomic_fetch_add(&a.done[r.k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + 1 != r.ntiles) return;
   }
-  const uint32_t b = t->succ_begin, e = b + t->nsucc;
+  const uint32_t b = r.succ_begin, e = b + r.nsucc;
   for (uint32_t s = b; s < e; ++s)
     __hip_atomic_fetch_add(&a.pending[a.succ[s]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (a.times) {
-    uint32_t left = __hip_atomic_fetch_sub(&a.comm_left[t->comm], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (left == 1) a.times[t->comm] = dev_clock();
+    uint32_t left = __hip_atomic_fetch_sub(&a.comm_left[r.comm], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (left == 1) a.times[r.comm] = dev_clock();
   }
 }
 
@@ -621,9 +639,11 @@ __device__ __forceinline__ void retire(const ExecArgs& a, const DevTask* t, uint
 // workgroup exits. The last workgroup to leave resets the counters.
 //
 // Each workgroup is BLOCK worker threads plus one scheduler wave. While the
-// workers stream tile i, the scheduler (lane 0) retires tile i-1, claims
-// tile i+1 and posts it in the other of two LDS slots, so claim / retire
-// latency hides behind data movement. The scheduler only posts a tile as
+// workers stream tile i, the scheduler claims tile i+1, copies its task
+// descriptor into the other of two LDS slots (so workers start streaming
+// without a global-memory round trip), retires tile i-1 and checks tile
+// i+1's readiness. The loads for tile i+1 are issued before tile i-1's
+// retire, so their latencies overlap. The scheduler only posts a tile as
 // ready once its predecessors have retired; if they have not after a few
 // polls it posts the tile as not ready: in the next iteration the workers
 // idle while the scheduler retires tile i (the tile may depend on it) and
@@ -659,9 +679,8 @@ __device__ __forceinline__ uint32_t claim_next(const ExecArgs& a, Claim& c) {
   return tl;
 }
 
-// Poll task k's predecessor count up to `polls` times; true once all retired.
-__device__ __forceinline__ bool poll_ready(const ExecArgs& a, uint32_t k, uint32_t polls) {
-  const uint32_t need = a.tasks[k].npred;
+// Poll task k's predecessor count up to `polls` times; true once all `need` retired.
+__device__ __forceinline__ bool poll_ready(const ExecArgs& a, uint32_t k, uint32_t need, uint32_t polls) {
   for (uint32_t i = 0; need; ++i) {
     if (__hip_atomic_load(&a.pending[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) return true;
     if (i + 1 >= polls) return false;
@@ -670,9 +689,8 @@ __device__ __forceinline__ bool poll_ready(const ExecArgs& a, uint32_t k, uint32
   return true;
 }
 
-// Bounded wait for task k's predecessors; false if the run aborts.
-__device__ __forceinline__ bool wait_ready(const ExecArgs& a, uint32_t k) {
-  const uint32_t need = a.tasks[k].npred;
+// Bounded wait for task k's `need` predecessors; false if the run aborts.
+__device__ __forceinline__ bool wait_ready(const ExecArgs& a, uint32_t k, uint32_t need) {
   if (!need) return true;
   uint32_t polls = 0;
   while (__hip_atomic_load(&a.pending[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
@@ -687,57 +705,100 @@ __device__ __forceinline__ bool wait_ready(const ExecArgs& a, uint32_t k) {
   return true;
 }
 
+// Scheduler-wave helpers (called by all 64 lanes of the scheduler wave).
+// Copy task k's 128-byte descriptor into an LDS slot: 8 lanes, 16 bytes each.
+__device__ __forceinline__ void stage_desc(DevTask* slot, const DevTask* src, uint32_t lane) {
+  if (lane < 8) reinterpret_cast<uint4*>(slot)[lane] = reinterpret_cast<const uint4*>(src)[lane];
+}
+__device__ __forceinline__ TileRef ref_of(const DevTask& t, uint32_t k) {
+  return TileRef{k, t.nsucc, t.succ_begin, t.ntiles, t.comm};
+}
+
 template <int BLOCK, bool NARROW>
 __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
+  __shared__ DevTask s_task[2];
   __shared__ uint32_t s_slot[2], s_flag;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x) / 64;   // wave-uniform
   const bool sched = wave == BLOCK / 64;
+  const uint32_t lane = threadIdx.x & 63u;
   const bool lead = threadIdx.x == BLOCK;                                  // the scheduler's lane 0
   Claim c{blockIdx.x % a.queues, 0, 0, 0};
+  TileRef cur_ref{}, prev_ref{};
   if (sched) {
-    if (lead) {
-      // nothing of this workgroup is in flight yet: a full wait cannot block on itself
-      uint32_t tl = claim_next(a, c);
-      if (tl != kNoTile && !wait_ready(a, a.tile_task[tl])) tl = kNoTile;
-      s_slot[0] = tl;
+    // nothing of this workgroup is in flight yet: a full wait cannot block on itself
+    uint32_t tl_l = kNoTile;
+    if (lead) tl_l = claim_next(a, c);
+    uint32_t tl = __builtin_amdgcn_readfirstlane(tl_l);
+    if (tl != kNoTile) {
+      const uint32_t k = __builtin_amdgcn_readfirstlane(a.tile_task[tl]);
+      stage_desc(&s_task[0], a.tasks + k, lane);
+      __builtin_amdgcn_s_waitcnt(0);   // the copy has landed before lane 0 reads it back
+      if (lead) {
+        cur_ref = ref_of(s_task[0], k);
+        if (!wait_ready(a, k, s_task[0].npred)) tl = kNoTile;
+      }
     }
+    if (lead) s_slot[0] = tl;
   }
   __syncthreads();
-  uint32_t cur = 0, prev = kNoTile;
+  uint32_t cur = 0;
+  bool have_prev = false;
   for (;;) {
     const uint32_t v = __builtin_amdgcn_readfirstlane(s_slot[cur]);
     if (v == kNoTile) break;
     const bool ready = (v & kNotReady) == 0;
     const uint32_t tl = v & ~kNotReady;
     if (sched) {
-      if (lead) {
-        if (prev != kNoTile) retire(a, a.tasks + a.tile_task[prev], a.tile_task[prev]);
-        uint32_t post;
-        if (ready) {
-          // the workers run tl now: claim the next tile; it may depend on tl, so do not block on it
-          const uint32_t nx = claim_next(a, c);
-          post = nx == kNoTile ? kNoTile : (poll_ready(a, a.tile_task[nx], 4) ? nx : (nx | kNotReady));
-        } else {
-          // the workers idle this iteration; everything of ours has retired, so wait in full
-          post = wait_ready(a, a.tile_task[tl]) ? tl : kNoTile;
+      DevTask* next = &s_task[cur ^ 1];
+      if (ready) {
+        // the workers run tl now: claim the next tile; it may depend on tl, so do not block on it
+        uint32_t nx_l = kNoTile;
+        if (lead) nx_l = claim_next(a, c);
+        const uint32_t nx = __builtin_amdgcn_readfirstlane(nx_l);
+        uint32_t k_l = nx != kNoTile ? a.tile_task[nx] : 0u;          // in flight during the retire below
+        if (lead && have_prev) retire(a, prev_ref);
+        const uint32_t knx = __builtin_amdgcn_readfirstlane(k_l);
+        uint32_t post = kNoTile;
+        if (nx != kNoTile) {
+          stage_desc(next, a.tasks + knx, lane);
+          uint32_t have_l = 0;
+          if (lead) have_l = __hip_atomic_load(&a.pending[knx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __builtin_amdgcn_s_waitcnt(0);
+          if (lead) {
+            const uint32_t need = next->npred;
+            const bool ok = need == 0 || have_l >= need || poll_ready(a, knx, need, 4);
+            post = ok ? nx : (nx | kNotReady);
+          }
         }
-        s_slot[cur ^ 1] = post;
+        if (lead) {
+          s_slot[cur ^ 1] = post;
+          prev_ref = cur_ref;
+          if (nx != kNoTile) cur_ref = ref_of(*next, knx);
+        }
+      } else {
+        // the workers idle this iteration; everything of ours has retired once
+        // tile i-1 has, so wait in full, then post tl again in the other slot
+        if (lead && have_prev) retire(a, prev_ref);
+        stage_desc(next, &s_task[cur], lane);
+        uint32_t post = kNoTile;
+        if (lead) post = wait_ready(a, cur_ref.k, s_task[cur].npred) ? tl : kNoTile;
+        if (lead) s_slot[cur ^ 1] = post;
       }
     } else if (ready) {
-      const uint32_t k = __builtin_amdgcn_readfirstlane(a.tile_task[tl]);
-      run_tile<BLOCK, NARROW>(a.tasks + k, tl);
+      const DevTask* t = &s_task[cur];
+      run_tile<BLOCK, NARROW>(t, tl);
       // a tile whose retire releases something (successors, a completion
       // stamp) has its stores complete before the barrier; any other tile's
       // stores drain while the next tile streams, and the kernel's end
       // orders them before the host or a later launch sees the buffers
-      if (a.tasks[k].nsucc || a.times) wait_mem();
+      if (uni32(t->nsucc) || a.times) wait_mem();
     }
-    prev = ready ? tl : kNoTile;
+    have_prev = ready;
     cur ^= 1;
     __syncthreads();
   }
   if (sched) {
-    if (lead && prev != kNoTile) retire(a, a.tasks + a.tile_task[prev], a.tile_task[prev]);
+    if (lead && have_prev) retire(a, prev_ref);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -770,12 +831,7 @@ __global__ __launch_bounds__(BLOCK) void hiccl_staged(ExecArgs a, uint32_t lo, u
   }
 }
 
-constexpr int kBlock = 256;          // stage launches; persistent executor with bf16 / fp8 tables
-// Worker threads of the persistent executor for int32 / float32 tables: 8
-// worker waves keep more loads in flight per compute unit at one workgroup
-// per unit (measured 0-3 % faster than 4); the bf16 / fp8 build needs too many
-// registers for 9 waves per workgroup and keeps 4 worker waves.
-constexpr int kBlockWide = 512;
+constexpr int kBlock = 256;
 
 // ------------------------------------------------------------- executable
 // An uploaded task table: one communicator, or a merged batch.
@@ -1018,7 +1074,7 @@ static int launch(const Exe& ex, hipStream_t st) {
     if (ex.narrow)
       hipLaunchKernelGGL((hiccl_persistent<kBlock, true>), dim3(ex.grid), dim3(kBlock + 64), 0, st, a);
     else
-      hipLaunchKernelGGL((hiccl_persistent<kBlockWide, false>), dim3(ex.grid), dim3(kBlockWide + 64), 0, st, a);
+      hipLaunchKernelGGL((hiccl_persistent<kBlock, false>), dim3(ex.grid), dim3(kBlock + 64), 0, st, a);
   } else {
     for (size_t s = 0; s + 1 < ex.stage_tile_begin.size(); ++s)
       if (int rc = launch_stage(ex, st, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1])) return rc;
