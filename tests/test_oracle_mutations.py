@@ -106,3 +106,29 @@ def test_wrong_bf16_rounding_is_caught(monkeypatch):
         return (np.ascontiguousarray(np.asarray(x, np.float32)).view(np.uint32) >> 16).astype(np.uint16)
     monkeypatch.setattr(OQ, "f32_to_bf16_bits", trunc)
     _fails(PQ.test_bf16_hand_values)
+
+
+def test_reversed_operand_order_is_caught(monkeypatch):
+    real = OT.reduction_tree
+
+    def reversed_children(leaves, root, h):
+        t = real(leaves, root, h)
+
+        def flip(n):
+            if isinstance(n, OT.Node):
+                n.children = list(reversed(n.children))
+                for ch in n.children:
+                    flip(ch)
+        flip(t)
+        return t
+    monkeypatch.setattr(OT, "reduction_tree", reversed_children)
+    from tests import test_oracle_reduce as PR
+    _fails(PR.test_tree_reduce_nesting_2x2)
+
+
+def test_dropped_leaf_in_tree_reduce_is_caught(monkeypatch):
+    real = OT.tree_reduce
+    monkeypatch.setattr(OT, "tree_reduce", lambda values, leaves, root, h, combine:
+                        real(values, list(leaves)[:-1] or list(leaves), root, h, combine))
+    from tests import test_oracle_reduce as PR
+    _fails(PR.test_tree_reduce_of_exact_integers_is_the_sum, [2, 2, 3])
