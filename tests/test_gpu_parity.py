@@ -315,3 +315,36 @@ def test_spin_limit_abort_is_clean_and_recoverable(torch_cuda):
         out = R.cpu().numpy()
         H.check_result(name, {r: out[r] for r in range(p)}, sends, "int32")
     c.close()
+
+
+@pytest.mark.parametrize("name,p,h", [("all_reduce", 1, [1]), ("broadcast", 1, [1]), ("all_reduce", 2, [1, 2]),
+                                      ("all_reduce", 4, [4, 1]), ("all_to_all", 3, [3]), ("reduce_scatter", 6, [3, 1, 2])])
+@pytest.mark.parametrize("mode", ["persistent", "staged"])
+def test_degenerate_hierarchies(torch_cuda, name, p, h, mode):
+    """One rank, unit factors and odd factors: the factorization degenerates to copies or flat levels."""
+    sends, outs = _run(torch_cuda, name, p, h, "int32", 37, seed=3, reps=2, mode=mode, tile=1024)
+    for out in outs:
+        H.check_result(name, _got(name, out, p, 0), sends, "int32", h=h)
+
+
+@pytest.mark.parametrize("mode", ["persistent", "staged"])
+def test_unaligned_operands(torch_cuda, mode):
+    """Buffers that start one element past a 16-byte boundary take the 4-byte (and byte) paths."""
+    torch = torch_cuda
+    from paper_2408_05962_amd import collectives as CO
+    name, p, h, d = "all_reduce", 8, [2, 4], 1000
+    sends = _host_inputs(name, p, d, "float32", 9)
+    n = H.send_len(name, p, d)
+    S = torch.zeros((p, n + 1), dtype=torch.float32, device="cuda")
+    S[:, 1:] = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+    R = torch.zeros((p, n + 1), dtype=torch.float32, device="cuda")
+    c = CO.make(name, p, "float32", [S[r, 1:] for r in range(p)], [R[r, 1:] for r in range(p)], d, hierarchy=h,
+                stripe=2, pipeline=3, exec_mode=mode, tile_bytes=2048)
+    c.set_spin_limit(1 << 20)
+    c.run(torch.cuda.current_stream())
+    c.wait()
+    torch.cuda.synchronize()
+    c.close()
+    out = R[:, 1:].cpu().numpy()
+    assert np.all(R[:, 0].cpu().numpy() == 0)           # nothing written before the buffers
+    H.check_result(name, {r: out[r] for r in range(p)}, sends, "float32", h=h, s=2)
