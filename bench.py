@@ -310,6 +310,35 @@ def sweep_bench(torch):
         _progress(f"ring {name}: {r}")
     out["ring_vs_tree_16r_4x4_64MiB"] = ring
 
+    # two-step rows of Table 2 (a fence and a scratch buffer of d*p per rank) against the single-step form
+    from paper_2408_05962_amd import Comm
+    two = {}
+    for name in ("broadcast", "reduce", "all_gather", "reduce_scatter", "all_reduce_bcast"):
+        base = "all_reduce" if name == "all_reduce_bcast" else name
+        snd = synth.device_buffers("float32", 7, P, send_len(base, P, d))
+        rcv = torch.zeros((P, recv_len(base, P, d)), device="cuda")
+        scr = torch.zeros((P, d * P), device="cuda")
+        c = Comm(P, "float32")
+        CO.compose_multi(c, name, [snd[r] for r in range(P)], [rcv[r] for r in range(P)], [scr[r] for r in range(P)],
+                         d, root=0)
+        c.set_hierarchy(HIER)
+        c.set_stripe(STRIPE)
+        c.set_pipeline(PIPE)
+        c.set_exec("staged")
+        c.init()
+        ms2 = _time_comm(torch, c)
+        info = c.plan_info()
+        c.close()
+        c = CO.make(base, P, "float32", [snd[r] for r in range(P)], [rcv[r] for r in range(P)], d, hierarchy=HIER,
+                    stripe=STRIPE, pipeline=PIPE, exec_mode="staged")
+        ms1 = _time_comm(torch, c)
+        c.close()
+        two[name] = {"two_step_ms": round(ms2, 4), "single_step_ms": round(ms1, 4),
+                     "two_step_exec_GBps": round((info["hbm_read"] + info["hbm_written"]) / ms2 / 1e6, 1)}
+        del snd, rcv, scr
+    out["two_step_vs_single_step"] = two
+    _progress(f"two-step: {two}")
+
     # Scatter / Gather at the headline shape
     sg = {}
     for name in ("scatter", "gather"):

@@ -348,3 +348,38 @@ def test_unaligned_operands(torch_cuda, mode):
     out = R[:, 1:].cpu().numpy()
     assert np.all(R[:, 0].cpu().numpy() == 0)           # nothing written before the buffers
     H.check_result(name, {r: out[r] for r in range(p)}, sends, "float32", h=h, s=2)
+
+
+@pytest.mark.parametrize("name", ["broadcast", "reduce", "all_gather", "reduce_scatter", "all_reduce_bcast"])
+@pytest.mark.parametrize("h,s,m", [([2, 4, 2], 4, 2), ([2, 3], 3, 1)])
+@pytest.mark.parametrize("mode", ["persistent", "staged"])
+def test_two_step_compositions(torch_cuda, name, h, s, m, mode):
+    """The two-step rows of Table 2 (a fence between the steps, an intermediate scratch buffer) on the
+    GPU, int32: equal to the direct definitions bit for bit."""
+    torch = torch_cuda
+    from paper_2408_05962_amd import Comm
+    from paper_2408_05962_amd import collectives as CO
+    p = int(np.prod(h))
+    d = 1000 + 3
+    base = "all_reduce" if name == "all_reduce_bcast" else name
+    sends = _host_inputs(base, p, d, "int32", zlib.crc32(f"two{name}{h}".encode()) % 1000)
+    S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+    R = torch.full((p, H.recv_len(base, p, d)), -7, dtype=torch.int32, device="cuda")
+    X = torch.zeros((p, d * p), dtype=torch.int32, device="cuda")
+    c = Comm(p, "int32")
+    CO.compose_multi(c, name, [S[r] for r in range(p)], [R[r] for r in range(p)], [X[r] for r in range(p)], d,
+                     root=p - 1)
+    c.set_hierarchy(h)
+    c.set_stripe(s)
+    c.set_pipeline(m)
+    c.set_exec(mode, 4096)
+    c.set_spin_limit(1 << 20)
+    c.init()
+    for _ in range(2):
+        R.fill_(-7)
+        c.run(torch.cuda.current_stream())
+        c.wait()
+        torch.cuda.synchronize()
+        out = R.cpu().numpy()
+        H.check_result(base, _got(base, out, p, p - 1), sends, "int32", root=p - 1)
+    c.close()
