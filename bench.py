@@ -111,7 +111,7 @@ def tune_table(torch, seed=9):
         for ci, (lo, hi) in enumerate(SIZE_CLASSES):
             size = int((lo * hi) ** 0.5) // (BATCH_P * 16) * (BATCH_P * 16)
             c, snd, rcv, _ = _mk(torch, CO, name, BATCH_P, BATCH_H, "float32", size, seed * 100 + ci)
-            r = autotune_model(c, [1, 2, 4], [1, 2, 4, 8], [16384, 65536], reps=3, anchors=4, top=3, stream=st)
+            r = autotune_model(c, [1, 2, 4], [1, 2, 4, 8], [16384, 65536], reps=3, anchors=5, top=3, stream=st)
             table[(name, ci)] = (r["stripe"], r["pipeline"], r["tile_bytes"])
             _progress(f"tuned {name} class {ci}: {table[(name, ci)]}")
             c.close()
@@ -338,6 +338,35 @@ def sweep_bench(torch):
         del snd, rcv, scr
     out["two_step_vs_single_step"] = two
     _progress(f"two-step: {two}")
+
+    # the model-guided autotuner against exhaustive search (24 candidates), persistent executor
+    from paper_2408_05962_amd import autotune, autotune_model
+    tun = {}
+    for size in (1 << 20, S_BYTES):
+        dd = size // 4 // P
+        for name in SIX:
+            snd = synth.device_buffers("float32", 11, P, send_len(name, P, dd))
+            rcv = torch.zeros((P, recv_len(name, P, dd)), device="cuda")
+            res = {}
+            for kind in ("exhaustive", "model"):
+                c = CO.make(name, P, "float32", [snd[r] for r in range(P)], [rcv[r] for r in range(P)], dd,
+                            hierarchy=HIER)
+                if kind == "exhaustive":
+                    r = autotune(c, [1, 2, 4], [1, 2, 4, 8], [16384, 65536], reps=3, stream=st)
+                    r["measured"] = 24
+                else:
+                    r = autotune_model(c, [1, 2, 4], [1, 2, 4, 8], [16384, 65536], reps=3, anchors=5, top=3, stream=st)
+                res[kind] = r
+                c.close()
+            tun[f"{name}/{size >> 20}MiB"] = {
+                "exhaustive_us": round(res["exhaustive"]["us"], 1), "model_us": round(res["model"]["us"], 1),
+                "model_over_exhaustive": round(res["model"]["us"] / res["exhaustive"]["us"], 3),
+                "model_measured": res["model"]["measured"],
+                "exhaustive_pick": [res["exhaustive"][k] for k in ("stripe", "pipeline", "tile_bytes")],
+                "model_pick": [res["model"][k] for k in ("stripe", "pipeline", "tile_bytes")]}
+            del snd, rcv
+    out["autotuner_model_vs_exhaustive"] = tun
+    _progress(f"autotuners: {tun}")
 
     # Scatter / Gather at the headline shape
     sg = {}

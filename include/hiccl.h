@@ -290,8 +290,9 @@ int hiccl_autotune(hiccl_comm_t comm, const int* stripes, int nstripes, const in
 /* Model-guided autotuner (prior in the spirit of the cost model of Sec. 4.6):
  * every candidate is planned on the host to obtain its executed bytes,
  * tiles and dependency stages; t = bytes / BW + a * tiles + b * stages + c
- * is fitted to `anchors` timed candidates (least squares), and only the
- * `top` best-predicted candidates are timed in addition. `measured`
+ * (nonnegative cost weights) is fitted by least squares to `anchors` timed
+ * candidates chosen far apart in that feature space, and only the `top`
+ * best-predicted candidates are timed in addition. `measured`
  * returns how many candidates ran on the device. Otherwise as
  * hiccl_autotune. */
 int hiccl_autotune_model(hiccl_comm_t comm, const int* stripes, int nstripes, const int* pipes, int npipes,

@@ -1386,13 +1386,17 @@ static double time_candidate(hiccl_comm_t comm, int s, int m, size_t tile, int r
 }
 
 // Least squares for y ~ X w with 4 unknowns (normal equations, Gaussian elimination).
-static bool fit4(const std::vector<std::array<double, 4>>& X, const std::vector<double>& y, double w[4]) {
+// Least squares for w over the features marked in `use` (others fixed at 0).
+static bool fit4_masked(const std::vector<std::array<double, 4>>& X, const std::vector<double>& y, const bool use[4],
+                        double w[4]) {
   double A[4][5] = {};
   for (size_t i = 0; i < X.size(); ++i)
     for (int r = 0; r < 4; ++r) {
-      for (int c = 0; c < 4; ++c) A[r][c] += X[i][r] * X[i][c];
-      A[r][4] += X[i][r] * y[i];
+      for (int c = 0; c < 4; ++c) A[r][c] += (use[r] && use[c]) ? X[i][r] * X[i][c] : 0.0;
+      A[r][4] += use[r] ? X[i][r] * y[i] : 0.0;
     }
+  for (int r = 0; r < 4; ++r)
+    if (!use[r]) A[r][r] = 1.0;                                         // w[r] = 0
   for (int r = 0; r < 4; ++r) A[r][r] += 1e-12 * (1.0 + A[r][r]);   // ridge against collinear anchors
   for (int c = 0; c < 4; ++c) {
     int piv = c;
@@ -1408,6 +1412,22 @@ static bool fit4(const std::vector<std::array<double, 4>>& X, const std::vector<
   }
   for (int r = 0; r < 4; ++r) w[r] = A[r][4] / A[r][r];
   return true;
+}
+
+// Cost model fit: time can only grow with bytes, tiles and stages, so a
+// cost weight that comes out negative (possible with few anchors) is fixed
+// at zero and the rest refitted.
+static bool fit4(const std::vector<std::array<double, 4>>& X, const std::vector<double>& y, double w[4]) {
+  bool use[4] = {true, true, true, true};
+  for (int round = 0; round < 3; ++round) {
+    if (!fit4_masked(X, y, use, w)) return false;
+    int worst = -1;
+    for (int r = 0; r < 3; ++r)
+      if (use[r] && w[r] < 0 && (worst < 0 || w[r] < w[worst])) worst = r;
+    if (worst < 0) return true;
+    use[worst] = false;
+  }
+  return fit4_masked(X, y, use, w);
 }
 }  // namespace hiccl
 
@@ -1444,13 +1464,38 @@ int hiccl_autotune_model(hiccl_comm_t comm, const int* stripes, int nstripes, co
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   int ran = 0;
-  // anchors spread over the candidate list (extremes first)
-  std::vector<size_t> order;
-  for (size_t i = 0; i < cs.size(); ++i) order.push_back(i);
+  // anchors spread over the feature space: start from the cheapest-looking
+  // candidate (fewest bytes + tiles + stages, normalized), then repeatedly
+  // take the candidate farthest from every anchor chosen so far
+  double mx[3] = {1e-30, 1e-30, 1e-30};
+  for (const Cand& k : cs)
+    for (int f = 0; f < 3; ++f) mx[f] = std::max(mx[f], k.x[f]);
+  auto dist2 = [&](const Cand& u, const Cand& v) {
+    double s = 0;
+    for (int f = 0; f < 3; ++f) s += (u.x[f] - v.x[f]) * (u.x[f] - v.x[f]) / (mx[f] * mx[f]);
+    return s;
+  };
   std::vector<size_t> anc;
-  for (int k = 0; k < anchors && k < int(cs.size()); ++k) {
-    size_t i = (anchors == 1) ? 0 : size_t(double(k) * double(cs.size() - 1) / double(anchors - 1) + 0.5);
-    if (std::find(anc.begin(), anc.end(), i) == anc.end()) anc.push_back(i);
+  size_t first = 0;
+  for (size_t i = 1; i < cs.size(); ++i)
+    if (cs[i].x[0] / mx[0] + cs[i].x[1] / mx[1] + cs[i].x[2] / mx[2] <
+        cs[first].x[0] / mx[0] + cs[first].x[1] / mx[1] + cs[first].x[2] / mx[2])
+      first = i;
+  anc.push_back(first);
+  while (int(anc.size()) < anchors && anc.size() < cs.size()) {
+    size_t far = cs.size();
+    double best_d = -1;
+    for (size_t i = 0; i < cs.size(); ++i) {
+      if (std::find(anc.begin(), anc.end(), i) != anc.end()) continue;
+      double d = 1e300;
+      for (size_t a : anc) d = std::min(d, dist2(cs[i], cs[a]));
+      if (d > best_d) {
+        best_d = d;
+        far = i;
+      }
+    }
+    if (far == cs.size()) break;
+    anc.push_back(far);
   }
   std::vector<std::array<double, 4>> X;
   std::vector<double> y;
