@@ -258,7 +258,9 @@ int hiccl_validate_host(hiccl_comm_t comm, uint64_t seed, int norders);
 
 typedef enum {
   HICCL_BATCH_PERSISTENT = 0,  /* all task tables merged into one persistent launch */
-  HICCL_BATCH_GRAPH = 1,       /* one launch per collective, captured once into a hipGraph and replayed */
+  HICCL_BATCH_GRAPH = 1,       /* captured once into a hipGraph and replayed: 4 parallel branches,
+                                  balanced by executed bytes, each running its collectives as stage
+                                  launches on a quarter of the device */
   HICCL_BATCH_SERIAL = 2,      /* one launch per collective on the stream (reference form) */
   HICCL_BATCH_PERSISTENT_SJF = 3, /* one merged launch, smallest collectives claimed first */
   HICCL_BATCH_STAGED = 4          /* task tables merged by dependency stage; one launch per stage for
@@ -273,9 +275,9 @@ int hiccl_batch_run(hiccl_batch_t batch, void* stream);
 int hiccl_batch_wait(hiccl_batch_t batch);
 /* Completion times (ns, relative to the batch start) of each collective of
  * the last run. Persistent forms: the device clock at the moment its last
- * task retired. Graph / serial: the device clock when its own launch
- * finished (UNSUPPORTED if a member runs on the staged executor). Staged:
- * stream events, the end of its last stage launch. `ns` has n entries. */
+ * task retired. Graph / serial: the device clock when its last launch
+ * finished. Staged: stream events, the end of its last stage launch. `ns`
+ * has n entries. */
 int hiccl_batch_times(hiccl_batch_t batch, uint64_t* ns, int n);
 int hiccl_batch_destroy(hiccl_batch_t batch);
 

@@ -821,6 +821,13 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
   }
 }
 
+// Device-clock stamp for stage launches (one thread): launched on the stream
+// before a collective's first stage and after its last, it records when the
+// collective started and finished.
+__global__ void hiccl_stamp(unsigned long long* at) {
+  if (threadIdx.x == 0) *at = wall_clock64();
+}
+
 // One launch per dependency stage: the kernel boundary orders the stages,
 // so no counters are used.
 template <int BLOCK, bool NARROW>
@@ -832,6 +839,7 @@ __global__ __launch_bounds__(BLOCK) void hiccl_staged(ExecArgs a, uint32_t lo, u
 }
 
 constexpr int kBlock = 256;
+constexpr int kGraphBranches = 4;     // parallel branches of the captured batch graph
 
 // ------------------------------------------------------------- executable
 // An uploaded task table: one communicator, or a merged batch.
@@ -1076,8 +1084,12 @@ static int launch(const Exe& ex, hipStream_t st) {
     else
       hipLaunchKernelGGL((hiccl_persistent<kBlock, false>), dim3(ex.grid), dim3(kBlock + 64), 0, st, a);
   } else {
+    // one collective with completion stamps (batch members): start, stages, end
+    const bool stamp = ex.d_times && ex.ncomm == 1;
+    if (stamp) hipLaunchKernelGGL(hiccl_stamp, dim3(1), dim3(64), 0, st, ex.d_times + 1);
     for (size_t s = 0; s + 1 < ex.stage_tile_begin.size(); ++s)
       if (int rc = launch_stage(ex, st, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1])) return rc;
+    if (stamp) hipLaunchKernelGGL(hiccl_stamp, dim3(1), dim3(64), 0, st, ex.d_times);
   }
   HIP_TRY(hipGetLastError());
   return 0;
@@ -1181,6 +1193,8 @@ struct hiccl_batch_s {
   Exe merged;                    // persistent form
   std::vector<Exe> each;         // graph / serial forms (per collective, with completion stamps)
   hipStream_t cap = nullptr;     // capture stream of the graph form
+  std::vector<hipStream_t> branch;   // graph form: extra capture streams, one per parallel branch
+  std::vector<int> branch_of;        // graph form: each collective's branch
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   hipEvent_t ev = nullptr;
@@ -1220,14 +1234,39 @@ static int batch_prepare(hiccl_batch_s* b) {
     b->each.resize(plans.size());
     for (size_t i = 0; i < plans.size(); ++i) {
       const ExecCfg& xi = b->comms[i]->c.exec;
-      if (int rc = upload({plans[i]}, {wsb[i]}, xi.mode, xi.grid, xi.spin_limit, true, b->each[i], xi.queues, xi.batch))
+      if (b->mode == HICCL_BATCH_GRAPH) {
+        // branches run side by side, each member as stage launches on a share
+        // of the device: stage launches need no residency guarantee (measured
+        // faster here than persistent members claiming from one queue)
+        const int g = std::max(1, 2 * cu_count() / kGraphBranches);
+        if (int rc = upload({plans[i]}, {wsb[i]}, HICCL_EXEC_STAGED, g, xi.spin_limit, true, b->each[i], 1, xi.batch))
+          return rc;
+      } else if (int rc = upload({plans[i]}, {wsb[i]}, xi.mode, xi.grid, xi.spin_limit, true, b->each[i], xi.queues,
+                                 xi.batch)) {
         return rc;
+      }
     }
   }
   int dev = 0, khz = 0;
   HIP_TRY(hipGetDevice(&dev));
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
     b->clock_hz = double(khz) * 1e3;
+  if (b->mode == HICCL_BATCH_GRAPH) {
+    // balance the branches by executed bytes, largest collective first
+    std::vector<size_t> idx(plans.size());
+    std::iota(idx.begin(), idx.end(), 0);
+    auto bytes = [&](size_t i) { return plans[i]->hbm_read + plans[i]->hbm_written; };
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return bytes(x) > bytes(y); });
+    const int nb = int(std::min<size_t>(kGraphBranches, plans.size()));
+    std::vector<uint64_t> load(nb, 0);
+    b->branch_of.assign(plans.size(), 0);
+    for (size_t i : idx) {
+      int k = int(std::min_element(load.begin(), load.end()) - load.begin());
+      b->branch_of[i] = k;
+      load[k] += bytes(i);
+    }
+    b->branch.assign(nb, nullptr);
+  }
   HIP_TRY(hipEventCreateWithFlags(&b->ev, hipEventDisableTiming));
   return 0;
 }
@@ -1271,16 +1310,36 @@ int hiccl_batch_run(hiccl_batch_t b, void* stream) {
       if (int rc = launch(e, st)) return rc;
   } else {
     if (!b->gexec) {
+      // one captured graph with parallel branches: branch 0 is the capture
+      // stream, the others fork from it and join back before the end
       HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+      const int nb = int(b->branch.size());
+      b->branch[0] = b->cap;
+      for (int k = 1; k < nb; ++k) HIP_TRY(hipStreamCreateWithFlags(&b->branch[k], hipStreamNonBlocking));
+      std::vector<hipEvent_t> evs(2 * size_t(nb), nullptr);
+      for (hipEvent_t& e : evs) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      auto cleanup = [&]() {
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+      };
       HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-      for (const Exe& e : b->each)
-        if (int rc = launch(e, b->cap)) {
-          hipGraph_t g = nullptr;
-          (void)hipStreamEndCapture(b->cap, &g);
-          if (g) (void)hipGraphDestroy(g);
-          return rc;
-        }
-      HIP_TRY(hipStreamEndCapture(b->cap, &b->graph));
+      int rc = 0;
+      HIP_TRY(hipEventRecord(evs[0], b->cap));
+      for (int k = 1; k < nb && !rc; ++k) rc = hipStreamWaitEvent(b->branch[k], evs[0], 0) == hipSuccess ? 0 : HICCL_ERR_HIP;
+      for (size_t i = 0; i < b->each.size() && !rc; ++i) rc = launch(b->each[i], b->branch[b->branch_of[i]]);
+      for (int k = 1; k < nb && !rc; ++k) {
+        rc = hipEventRecord(evs[size_t(nb) + k], b->branch[k]) == hipSuccess ? 0 : HICCL_ERR_HIP;
+        if (!rc) rc = hipStreamWaitEvent(b->cap, evs[size_t(nb) + k], 0) == hipSuccess ? 0 : HICCL_ERR_HIP;
+      }
+      if (rc) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(b->cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        cleanup();
+        return rc == HICCL_ERR_HIP ? fail(HICCL_ERR_HIP, "graph capture failed") : rc;
+      }
+      hipError_t ec = hipStreamEndCapture(b->cap, &b->graph);
+      cleanup();
+      HIP_TRY(ec);
       HIP_TRY(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
     }
     HIP_TRY(hipGraphLaunch(b->gexec, st));
@@ -1329,9 +1388,6 @@ int hiccl_batch_times(hiccl_batch_t b, uint64_t* ns, int n) {
     for (int i = 0; i < n; ++i) stamp[i] = t[i];
     start.push_back(t[n]);
   } else {
-    for (int i = 0; i < n; ++i)
-      if (b->each[i].mode != HICCL_EXEC_PERSISTENT)
-        return fail(HICCL_ERR_UNSUPPORTED, "graph / serial batch times need every member on the persistent executor");
     for (int i = 0; i < n; ++i) {
       unsigned long long t[2];
       HIP_TRY(hipMemcpy(t, b->each[i].d_times, sizeof(t), hipMemcpyDeviceToHost));
@@ -1354,6 +1410,8 @@ int hiccl_batch_destroy(hiccl_batch_t b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (size_t k = 1; k < b->branch.size(); ++k)
+    if (b->branch[k]) (void)hipStreamDestroy(b->branch[k]);
   if (b->ev) (void)hipEventDestroy(b->ev);
   delete b;
   return HICCL_SUCCESS;
