@@ -64,8 +64,9 @@ def is_sum(name, op):
     return op == "sum" and name in ("reduce", "reduce_scatter", "all_reduce")
 
 
-def _striped_ring(vals, root, n, h, s, ring, align):
-    """float32 R(all, root) under ring(ring) and stripe(s): per stripe, the ring reduction of its owner."""
+def _striped_ring(vals, root, n, h, s, ring, align, combine=OT.sum_f32, concat=np.concatenate):
+    """R(all, root) under ring(ring) and stripe(s): per stripe, the ring reduction of its owner, each node
+    formed by `combine` (default: float32 left-to-right sums)."""
     p = len(vals)
     k = OT.ring_depth(h, ring)
     size = OT.block_sizes(h)[k]
@@ -80,14 +81,14 @@ def _striped_ring(vals, root, n, h, s, ring, align):
                     own = [lo + ((root - lo) + t * (sz // s)) % sz for t in range(s)]
                 break
     if own is None:
-        return OT.ring_reduce(vals, range(p), root, h, ring, OT.sum_f32)
+        return OT.ring_reduce(vals, range(p), root, h, ring, combine)
     parts = []
     for t, (off, ln) in enumerate(OT.split(n, s, align)):
         if ln == 0:
             continue
         sub = {r: v[off:off + ln] for r, v in vals.items()}
-        parts.append(OT.ring_reduce(sub, range(p), own[t], h, ring, OT.sum_f32))
-    return np.concatenate(parts)
+        parts.append(OT.ring_reduce(sub, range(p), own[t], h, ring, combine))
+    return concat(parts)
 
 
 def tree_order_f32(name, sends, h, s, root=0, ring=1):
@@ -187,7 +188,7 @@ def _concat(parts, dtype):
     return Fp8Buf(np.concatenate([p.codes for p in parts]), np.concatenate([p.scales for p in parts]))
 
 
-def tree_order_payload(name, payloads, h, s):
+def tree_order_payload(name, payloads, h, s, ring=1):
     """Result of RS / AR / Reduce in a payload format: every reduction node widens its operands to
     float32, sums them left to right and narrows the result (fresh block scales for fp8), in the tree
     order of the factorization; transfers move payload bytes unchanged."""
@@ -197,6 +198,8 @@ def tree_order_payload(name, payloads, h, s):
     n = len(payloads[0])
 
     def striped(vals, root, m):
+        if ring > 1:
+            return _striped_ring(vals, root, m, h, s, ring, align, _node(dtype), lambda parts: _concat(parts, dtype))
         own = OT.stripe_owners(root, range(p), h, s)
         if own is None:
             return OT.tree_reduce(vals, range(p), root, h, _node(dtype))

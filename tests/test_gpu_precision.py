@@ -66,7 +66,7 @@ def test_payload_conversion_matches_oracle(torch_cuda):
     assert np.array_equal(Z.cpu().numpy().astype(np.float64), OQ.fp8_dequantize(c, s))
 
 
-def _run_payload(torch, name, dtype, X, h, s, m, d):
+def _run_payload(torch, name, dtype, X, h, s, m, d, ring=1):
     from paper_2408_05962_amd import collectives as CO
     p = X.shape[0]
     Y, Sc = _payload_tensors(torch, X, dtype)
@@ -81,7 +81,7 @@ def _run_payload(torch, name, dtype, X, h, s, m, d):
         RS = torch.zeros((p, rl // 256), dtype=torch.float32, device="cuda")
         send = [(Y[r], Sc[r]) for r in range(p)]
         recv = [(R[r], RS[r]) for r in range(p)]
-    c = CO.make(name, p, dtype, send, recv, d, hierarchy=h, stripe=s, pipeline=m)
+    c = CO.make(name, p, dtype, send, recv, d, hierarchy=h, stripe=s, pipeline=m, ring=ring)
     c.set_spin_limit(1 << 20)
     c.run(torch.cuda.current_stream())
     c.wait()
@@ -245,3 +245,28 @@ def test_fp8_node_every_code_pair(torch_cuda):
     got = R[0].cpu().numpy()
     bad = np.nonzero(got != ec)[0]
     assert bad.size == 0, f"{bad.size} codes differ, first at {bad[:5]}: got {got[bad[:5]]} want {ec[bad[:5]]}"
+
+
+@pytest.mark.parametrize("dtype", ["bfloat16", "fp8_e4m3"])
+@pytest.mark.parametrize("name", ["all_reduce", "reduce_scatter", "reduce"])
+@pytest.mark.parametrize("h,s,m,ring", [([4, 2], 1, 2, 4), ([4, 2], 2, 1, 4), ([2, 4, 2], 2, 2, 2)])
+def test_payload_collectives_with_ring_bit_exact(torch_cuda, dtype, name, h, s, m, ring):
+    """Payload formats under the hybrid ring+tree factorization (Sec. 4.4): each node of the ring order
+    widens, sums and narrows exactly as the oracle's ring reduction emulates it."""
+    torch = torch_cuda
+    import synth
+    p = int(np.prod(h))
+    d = 256 * max(s, 1) * 2
+    X = synth.device_buffers("float32_outliers", 60 + p + ring, p, d * p)
+    Y, Sc, R, RS = _run_payload(torch, name, dtype, X, h, s, m, d, ring=ring)
+    yh, sh = Y.cpu().numpy(), (Sc.cpu().numpy() if Sc is not None else [None] * p)
+    pay = [_host_payload(dtype, yh[r], sh[r]) for r in range(p)]
+    exp = H.tree_order_payload(name, pay, h, s, ring=ring)
+    rh, rsh = R.cpu().numpy(), (RS.cpu().numpy() if RS is not None else [None] * p)
+    for r, e in exp.items():
+        got = _host_payload(dtype, rh[r], rsh[r])
+        if dtype == "bfloat16":
+            assert np.array_equal(got, e), f"{name} {dtype} rank {r}"
+        else:
+            assert np.array_equal(got.codes, e.codes) and np.array_equal(got.scales, e.scales), f"{name} {dtype} rank {r}"
+

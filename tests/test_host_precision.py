@@ -52,3 +52,32 @@ def test_payload_plans_match_oracle(dtype, name, h, s, m):
         rep = OC.error_report(got, exact[r], scale[r])
         # stated, not a pass criterion of the method; a loose sanity bound only
         assert rep["scaled"] < (0.05 if dtype == "bfloat16" else 0.5)
+
+
+@pytest.mark.parametrize("dtype", ["bfloat16", "fp8_e4m3"])
+@pytest.mark.parametrize("name", ["all_reduce", "reduce_scatter", "reduce"])
+@pytest.mark.parametrize("h,s,m,ring", [([4, 2], 1, 2, 4), ([4, 2], 2, 1, 4), ([2, 4, 2], 2, 2, 2)])
+def test_payload_ring_host_schedule(dtype, name, h, s, m, ring):
+    """Payload formats under ring + tree: the library's host schedule checker (random dependency orders)
+    equals the oracle's per-node requantization in ring order."""
+    from paper_2408_05962_amd import collectives as CO
+    p = int(np.prod(h))
+    d = 256 * s * 2
+    rng = np.random.default_rng(p + ring)
+    X = (rng.standard_normal((p, d * p)) * np.where(rng.random((p, d * p)) < 0.01, 1e3, 1.0)).astype(np.float32)
+    pay = [H.to_payload_host(X[r], dtype) for r in range(p)]
+    rl = H.recv_len(name, p, d)
+    if dtype == "bfloat16":
+        send = [np.ascontiguousarray(pay[r]) for r in range(p)]
+        recv = [np.zeros(rl, np.uint16) for _ in range(p)]
+    else:
+        send = [(np.ascontiguousarray(pay[r].codes), np.ascontiguousarray(pay[r].scales)) for r in range(p)]
+        recv = [(np.zeros(rl, np.uint8), np.zeros(rl // 256, np.float32)) for _ in range(p)]
+    c = CO.make(name, p, dtype, send, recv, d, hierarchy=h, stripe=s, pipeline=m, ring=ring)
+    c.validate_host(seed=1, norders=2)
+    c.close()
+    for r, e in H.tree_order_payload(name, pay, h, s, ring=ring).items():
+        if dtype == "bfloat16":
+            assert np.array_equal(recv[r], e), (name, r)
+        else:
+            assert np.array_equal(recv[r][0], e.codes) and np.array_equal(recv[r][1], e.scales), (name, r)
