@@ -320,12 +320,16 @@ int hiccl_server_stream(hiccl_server_t srv, uint64_t ticket, void** stream);
 /* Start an admitted request: enqueue `comm` (initialized) on its slot. It
  * sets the request's grid (hiccl_set_grid): the executor's full default
  * when no other request is running, else about 3 x compute units / slots
- * workgroups, so that concurrent requests overlap on the device. */
+ * workgroups, so that concurrent requests overlap on the device. If the
+ * launch fails, the ticket is released (slot and budget) and the error
+ * returned. */
 int hiccl_server_launch(hiccl_server_t srv, uint64_t ticket, hiccl_comm_t comm);
 /* Retire finished requests (frees their slots and budget); non-blocking. */
 int hiccl_server_progress(hiccl_server_t srv);
 /* done = 1 once the request has finished; device_us = its time on the
- * device, launch to completion, from stream events. */
+ * device, launch to completion, from stream events. A finished ticket is
+ * forgotten after this call; if its run gave up a dependency wait, the call
+ * returns TIMEOUT (with done = 1). */
 int hiccl_server_poll(hiccl_server_t srv, uint64_t ticket, int* done, double* device_us);
 /* Block until every launched request has finished and retire them. */
 int hiccl_server_drain(hiccl_server_t srv);

@@ -19,6 +19,8 @@ struct hiccl_server_s {
     bool launched = false, done = false;
     hipEvent_t start = nullptr, stop = nullptr;
     double device_us = 0;
+    hiccl_comm_t comm = nullptr;        // the launched communicator
+    int status = HICCL_SUCCESS;         // its run's outcome once done
   };
   size_t budget = 0, used = 0;
   std::vector<hipStream_t> streams;
@@ -108,13 +110,22 @@ int hiccl_server_launch(hiccl_server_t s, uint64_t ticket, hiccl_comm_t comm) {
   int running = 0;
   for (const auto& kv : s->reqs) running += kv.second.launched && !kv.second.done;
   if (int rc = hiccl_set_grid(comm, running ? s->share_grid : 0)) return rc;
-  HIP_OK(hipEventCreate(&r.start), "event");
-  HIP_OK(hipEventCreate(&r.stop), "event");
-  HIP_OK(hipEventRecord(r.start, st), "event record");
-  int rc = hiccl_run(comm, st);
-  if (rc) return rc;
-  HIP_OK(hipEventRecord(r.stop, st), "event record");
+  // a launch that fails releases its ticket (slot and budget), so the caller can admit again
+  auto give_up = [&](int rc) {
+    if (r.start) (void)hipEventDestroy(r.start);
+    if (r.stop) (void)hipEventDestroy(r.stop);
+    r.start = r.stop = nullptr;
+    release(s, ticket, r);
+    s->reqs.erase(it);
+    return rc;
+  };
+  if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess ||
+      hipEventRecord(r.start, st) != hipSuccess)
+    return give_up(fail(HICCL_ERR_HIP, "request events"));
+  if (int rc = hiccl_run(comm, st)) return give_up(rc);
+  if (hipEventRecord(r.stop, st) != hipSuccess) return give_up(fail(HICCL_ERR_HIP, "request event record"));
   r.launched = true;
+  r.comm = comm;
   return HICCL_SUCCESS;
 }
 
@@ -128,6 +139,7 @@ int hiccl_server_progress(hiccl_server_t s) {
     if (q != hipSuccess) return fail(HICCL_ERR_HIP, std::string("request failed: ") + hipGetErrorString(q));
     float ms = 0;
     if (hipEventElapsedTime(&ms, r.start, r.stop) == hipSuccess) r.device_us = ms * 1e3;
+    r.status = hiccl_wait(r.comm);      // finished: reads the run's status (TIMEOUT if a wait expired)
     r.done = true;
     release(s, kv.first, r);
     (void)hipEventDestroy(r.start);
@@ -144,8 +156,13 @@ int hiccl_server_poll(hiccl_server_t s, uint64_t ticket, int* done, double* devi
   if (it == s->reqs.end()) return fail(HICCL_ERR_INVALID_ARG, "unknown ticket");
   if (done) *done = it->second.done ? 1 : 0;
   if (device_us) *device_us = it->second.device_us;
-  if (it->second.done) s->reqs.erase(it);
-  return HICCL_SUCCESS;
+  int rc = HICCL_SUCCESS;
+  if (it->second.done) {
+    rc = it->second.status;
+    s->reqs.erase(it);
+    if (rc) return fail(rc, "the request's executor gave up a dependency wait (spin limit reached)");
+  }
+  return rc;
 }
 
 int hiccl_server_drain(hiccl_server_t s) {

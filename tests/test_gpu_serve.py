@@ -99,3 +99,52 @@ def test_admission_errors(torch_cuda):
     assert b is not None
     assert srv.admit(10) is None           # both slots taken
     srv.close()
+
+
+def test_failed_launch_releases_and_timeouts_are_reported(torch_cuda):
+    """A launch that fails gives its slot and budget back; a request whose executor gives up a
+    dependency wait (forced from the host with a one-poll spin limit) is reported by poll as TIMEOUT,
+    and the same template then serves correctly again."""
+    torch = torch_cuda
+    from paper_2408_05962_amd import Comm, Server
+    from paper_2408_05962_amd import collectives as CO
+    from paper_2408_05962_amd.hiccl import ERR_STATE, ERR_TIMEOUT, HicclError
+    srv = Server(1 << 30, 2)
+    bad = Comm(4, "float32")                     # never initialized: hiccl_run refuses it
+    tk = srv.admit(1 << 20)
+    with pytest.raises(HicclError) as e:
+        srv.launch(tk, bad)
+    assert e.value.code == ERR_STATE
+    assert srv.usage() == (0, 0)                 # the ticket was released
+    bad.close()
+    p, h, d = 16, [2, 4, 2], 4096
+    sends = [np.random.default_rng(r).integers(-1000, 1001, d * p).astype(np.int32) for r in range(p)]
+    S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+    R = torch.zeros_like(S)
+    c = CO.make("all_reduce", p, "int32", [S[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=h,
+                stripe=4, pipeline=2, tile_bytes=1024)
+    c.set_claim(1, 4)
+    c.set_spin_limit(1)
+    timeouts = 0
+    for _ in range(3):
+        tk = srv.admit(1 << 20)
+        srv.launch(tk, c)
+        srv.drain()
+        try:
+            srv.poll(tk)
+        except HicclError as err:
+            assert err.code == ERR_TIMEOUT
+            timeouts += 1
+    assert timeouts > 0
+    c.set_spin_limit(1 << 20)
+    R.zero_()
+    tk = srv.admit(1 << 20)
+    srv.launch(tk, c)
+    srv.drain()
+    done, _ = srv.poll(tk)
+    assert done
+    torch.cuda.synchronize()
+    out = R.cpu().numpy()
+    H.check_result("all_reduce", {r: out[r] for r in range(p)}, sends, "int32")
+    srv.close()
+    c.close()
