@@ -259,8 +259,8 @@ def _time_comm(torch, c, reps=10, warm=2):
 
 
 def sweep_bench(torch):
-    """Measurements beside the headline: pipeline depth, ring vs tree, Scatter / Gather, and the small
-    All-Reduce's latency."""
+    """Measurements beside the headline: pipeline depth, ring vs tree, two-step compositions, the
+    autotuners, Scatter / Gather, one rank's share, and the small All-Reduce's latency."""
     import numpy as np
 
     import synth
@@ -380,6 +380,39 @@ def sweep_bench(torch):
         del snd, rcv
     out["scatter_gather"] = sg
     _progress(f"scatter/gather: {sg}")
+
+    # one rank's share at the headline shape: the tasks whose output lies in rank r's memory, i.e. the
+    # work one GPU would do if each virtual rank were its own GPU pulling remote operands (Sec. 5.1)
+    shares = {}
+    for name in SIX:
+        c, snd, rcv = mk(name, HIER, STRIPE, PIPE, "staged")
+        info = c.plan_info()
+        full_ms = _time_comm(torch, c)
+        W = torch.empty(max(c.workspace_size(), 256), dtype=torch.uint8, device="cuda")
+        c.set_workspace(W, W.numel())
+        c.run(st)
+        c.wait()
+        per = []
+        for r in range(P):
+            sc = CO.make(name, P, "float32", [snd[q] for q in range(P)], [rcv[q] for q in range(P)], d,
+                         hierarchy=HIER, stripe=STRIPE, pipeline=PIPE, exec_mode="staged", share=r)
+            sc.set_workspace(W, W.numel())
+            si = sc.plan_info()
+            per.append((_time_comm(torch, sc), si["hbm_read"] + si["hbm_written"], si["nstages"]))
+            sc.close()
+        k = max(range(P), key=lambda r: per[r][0])
+        shares[name] = {"full_ms": round(full_ms, 4),
+                        "full_exec_GB": round((info["hbm_read"] + info["hbm_written"]) / 1e9, 3),
+                        "max_share_ms": round(per[k][0], 4), "max_share_rank": k,
+                        "max_share_exec_GB": round(per[k][1] / 1e9, 3), "max_share_stages": per[k][2],
+                        "max_share_exec_GBps": round(per[k][1] / per[k][0] / 1e6, 1),
+                        "mean_share_ms": round(float(np.mean([x[0] for x in per])), 4),
+                        "sum_share_ms": round(float(np.sum([x[0] for x in per])), 4),
+                        "largest_share_exec_GB": round(max(x[1] for x in per) / 1e9, 3)}
+        c.close()
+        del snd, rcv, W
+        _progress(f"rank shares {name}: {shares[name]}")
+    out["one_rank_share_16r_64MiB_staged"] = shares
 
     # the small All-Reduce: 4 ranks as {2,2}, 65,536 int32 per rank, s = m = 1 (latency-bound)
     small = {}
@@ -524,7 +557,7 @@ def precision_bench(torch, reps=5, n=1 << 28, sample_blocks=64):
 SERVE_HIERS = [[2, 4], [2, 4, 2], [4, 4]]
 
 
-def serve_bench(torch, ntemplates=48, nreq=400, fractions=(0.25, 0.5, 0.75, 0.9, 1.2), slots=4,
+def serve_bench(torch, ntemplates=48, nreq=2000, fractions=(0.25, 0.5, 0.75, 0.9, 1.2), slots=4,
                 budget=200 * 10 ** 9, seed=8, mode="persistent"):
     """Poisson stream of collective requests over resident request templates.
 
@@ -659,7 +692,8 @@ def main():
                     help="executor of the serving templates")
     ap.add_argument("--precision", action="store_true", help="also measure the precision form (bf16 / fp8)")
     ap.add_argument("--sweep", action="store_true",
-                    help="also measure pipeline depth, ring vs tree, Scatter / Gather and the small All-Reduce")
+                    help="also measure pipeline depth, ring vs tree, two-step compositions, the autotuners, "
+                         "Scatter / Gather, one rank's share and the small All-Reduce")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the virtual ranks of the hierarchy "

@@ -141,12 +141,30 @@ int hiccl_set_hierarchy(hiccl_comm_t comm, const int* factors, int nlevels);
 int hiccl_set_stripe(hiccl_comm_t comm, int s);
 
 /* Ring length n across top-level groups (Sec. 4.4). n = 1 is the tree.
- * n > 1 must divide the first hierarchy factor. Default 1. */
+ * n > 1 must make nranks / n the size of a group of the hierarchy (n is a
+ * product of leading factors), and the stripe factor must divide that
+ * group; hiccl_init returns INVALID_ARG otherwise. Default 1. */
 int hiccl_set_ring(hiccl_comm_t comm, int n);
 
 /* Pipeline depth m (Sec. 4.1 item 5, Sec. 4.5): every branch is split into
  * m channels. Default 1. */
 int hiccl_set_pipeline(hiccl_comm_t comm, int m);
+
+/* One rank's share (not a paper parameter: a measurement aid). With
+ * rank >= 0, hiccl_init plans only the tasks whose output lies in that
+ * virtual rank's memory (its receive buffers or its workspace region): the
+ * work one GPU would do if every rank were its own GPU and each GPU ran the
+ * hops and reduce nodes it receives, pulling remote operands (the IPC get
+ * of Sec. 5.1). Edges from
+ * tasks of other ranks are dropped and the remaining stages renumbered, so
+ * the kept tasks read whatever their inputs hold when they run; the result
+ * is the collective's only where those inputs already hold their final
+ * values (for example after a run of the full plan on the same workspace).
+ * Byte accounting covers the kept tasks. hiccl_validate_host returns
+ * HICCL_ERR_STATE for such a plan. rank = -1 (default) plans the whole
+ * collective; values outside [-1, nranks) return INVALID_ARG. Like the
+ * other set calls it discards an existing plan. */
+int hiccl_set_share(hiccl_comm_t comm, int rank);
 
 /* Executor launch options (not a paper parameter): form (hiccl_exec_mode),
  * tile size in bytes (work unit of one workgroup; 0 = default: 64 KiB for

@@ -134,7 +134,7 @@ def compose_multi(comm: Comm, name: str, send, recv, scratch, d: int, root: int 
 
 def make(name: str, p: int, dtype, send, recv, d: int, hierarchy=None, stripe: int = 1, pipeline: int = 1,
          root: int = 0, op: str = "sum", form: str = "listing", exec_mode: str = "persistent", tile_bytes: int = 0,
-         grid: int = 0, order: str = "stage", init: bool = True, ring: int = 1) -> Comm:
+         grid: int = 0, order: str = "stage", init: bool = True, ring: int = 1, share: int = -1) -> Comm:
     """Create, compose and (by default) initialize a communicator for one collective."""
     c = Comm(p, dtype)
     compose(c, name, send, recv, d, root=root, op=op, form=form)
@@ -143,6 +143,8 @@ def make(name: str, p: int, dtype, send, recv, d: int, hierarchy=None, stripe: i
     c.set_ring(ring)
     c.set_pipeline(pipeline)
     c.set_exec(exec_mode, tile_bytes, grid, order)
+    if share >= 0:
+        c.set_share(share)
     if init:
         c.init()
     return c

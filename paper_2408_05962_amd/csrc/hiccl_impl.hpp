@@ -127,6 +127,7 @@ struct Comm {
   int step = 0;
   std::vector<int> hier;
   int stripe = 1, ring = 1, pipe = 1;
+  int share = -1;                // plan only this rank's tasks (-1: all)
   ExecCfg exec;
   bool planned = false;
   Plan plan;

@@ -585,6 +585,38 @@ static void build_edges(std::vector<Task>& ts, uint64_t& nedges) {
   }
 }
 
+// One rank's share: the tasks whose output lies in rank r's memory, in
+// program order. Edges from dropped tasks go (on separate GPUs they would be
+// flags set by a peer) and the stages left are renumbered densely; every
+// kept edge still runs from a lower stage to a higher one.
+static void keep_share(std::vector<Task>& ts, int r, uint64_t& nedges) {
+  std::vector<int> to(ts.size(), -1);
+  std::vector<Task> kept;
+  for (size_t i = 0; i < ts.size(); ++i)
+    if (ts[i].dst_rank == r) {
+      to[i] = int(kept.size());
+      kept.push_back(std::move(ts[i]));
+    }
+  std::vector<int> stages;
+  for (const Task& t : kept) stages.push_back(t.stage);
+  std::sort(stages.begin(), stages.end());
+  stages.erase(std::unique(stages.begin(), stages.end()), stages.end());
+  auto remap = [&](std::vector<int>& v) {
+    std::vector<int> o;
+    for (int x : v)
+      if (to[x] >= 0) o.push_back(to[x]);
+    v.swap(o);
+  };
+  nedges = 0;
+  for (Task& t : kept) {
+    remap(t.preds);
+    remap(t.succs);
+    nedges += t.preds.size();
+    t.stage = int(std::lower_bound(stages.begin(), stages.end(), t.stage) - stages.begin());
+  }
+  ts = std::move(kept);
+}
+
 void order_and_tile(Plan& p, int order, size_t tile_bytes) {
   std::vector<Task>& ts = p.tasks;
   size_t n = ts.size();
@@ -693,6 +725,7 @@ int build_plan(Comm& c) {
   int rc = factorize_all(c, pl.tasks, ws);
   if (rc) return rc;
   build_edges(pl.tasks, pl.nedges);
+  if (c.share >= 0) keep_share(pl.tasks, c.share, pl.nedges);
   // tile indices are 32-bit on the device
   uint64_t tiles = 0;
   for (const Task& t : pl.tasks) {
@@ -1103,6 +1136,14 @@ int hiccl_set_pipeline(hiccl_comm_t comm, int m) {
   return HICCL_SUCCESS;
 }
 
+int hiccl_set_share(hiccl_comm_t comm, int rank) {
+  CHECK_COMM(comm);
+  if (rank < -1 || rank >= comm->c.P) return fail(HICCL_ERR_INVALID_ARG, "share rank must be -1 or a rank");
+  unplan(comm->c);
+  comm->c.share = rank;
+  return HICCL_SUCCESS;
+}
+
 int hiccl_set_exec(hiccl_comm_t comm, int mode, size_t tile_bytes, int grid, int order) {
   CHECK_COMM(comm);
   if (mode != HICCL_EXEC_PERSISTENT && mode != HICCL_EXEC_STAGED) return fail(HICCL_ERR_INVALID_ARG, "bad mode");
@@ -1255,6 +1296,7 @@ int hiccl_plan_tasks(hiccl_comm_t comm, hiccl_task_info_t* out, size_t cap, size
 int hiccl_validate_host(hiccl_comm_t comm, uint64_t seed, int norders) {
   CHECK_COMM(comm);
   if (!comm->c.planned) return fail(HICCL_ERR_STATE, "call hiccl_init first");
+  if (comm->c.share >= 0) return fail(HICCL_ERR_STATE, "the schedule check needs the whole plan, not one rank's share");
   return validate_host(comm->c, seed, norders);
 }
 

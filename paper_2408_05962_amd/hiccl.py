@@ -73,6 +73,7 @@ def lib():
             "hiccl_set_stripe": [vp, i],
             "hiccl_set_ring": [vp, i],
             "hiccl_set_pipeline": [vp, i],
+            "hiccl_set_share": [vp, i],
             "hiccl_set_exec": [vp, i, sz, i, i],
             "hiccl_set_spin_limit": [vp, C.c_uint32],
             "hiccl_set_claim": [vp, i, i],
@@ -201,6 +202,9 @@ class Comm:
 
     def set_pipeline(self, m):
         return check(lib().hiccl_set_pipeline(self.h, int(m)))
+
+    def set_share(self, rank=-1):
+        return check(lib().hiccl_set_share(self.h, int(rank)))
 
     def set_exec(self, mode="persistent", tile_bytes=0, grid=0, order="stage"):
         return check(lib().hiccl_set_exec(self.h, EXEC.get(mode, mode), int(tile_bytes), int(grid),

@@ -291,3 +291,49 @@ def test_tile_limits(hc):
     c.init()
     assert c.plan_info()["ntiles"] == (1 << 39) // (1 << 20)
     c.close()
+
+
+@pytest.mark.parametrize("name", H.EIGHT)
+def test_rank_shares_partition_the_plan(hc, name):
+    """One rank's share keeps exactly the full plan's tasks whose output lies in that rank's memory, in
+    the same claim order and with stages renumbered densely; the shares of all ranks partition the
+    plan, its executed bytes and its edges' endpoints."""
+    from paper_2408_05962_amd import collectives as CO
+    p, d, h = 16, 256, [2, 4, 2]
+    send, recv = _bufs(p, H.send_len(name, p, d)), _bufs(p, H.recv_len(name, p, d))
+    kw = dict(hierarchy=h, stripe=4, pipeline=2, root=5, tile_bytes=1024)
+    full = CO.make(name, p, "float32", send, recv, d, **kw)
+    ft, fi = full.plan_tasks(), full.plan_info()
+    full.close()
+
+    def key(t):
+        return (t["kind"], t["prim"], t["step"], t["stripe"], t["channel"], t["dst_rank"], t["dst_workspace"],
+                tuple(t["src_rank"]), t["count"], t["offset"], t["ring_step"])
+
+    ntasks = rd = wr = 0
+    for r in range(p):
+        c = CO.make(name, p, "float32", send, recv, d, share=r, **kw)
+        st, si = c.plan_tasks(), c.plan_info()
+        mine = [t for t in ft if t["dst_rank"] == r]
+        assert [key(t) for t in st] == [key(t) for t in mine]
+        # dense stages, a monotone renumbering of the full plan's, and edges only among kept tasks
+        assert sorted({t["stage"] for t in st}) == list(range(si["nstages"]))
+        remap = {s: i for i, s in enumerate(sorted({t["stage"] for t in mine}))}
+        assert [t["stage"] for t in st] == [remap[t["stage"]] for t in mine]
+        assert all(a["npred"] <= b["npred"] for a, b in zip(st, mine))
+        assert si["workspace_bytes"] == fi["workspace_bytes"]
+        assert _code(c.validate_host) == hc.ERR_STATE
+        ntasks += si["ntasks"]
+        rd += si["hbm_read"]
+        wr += si["hbm_written"]
+        c.close()
+    assert (ntasks, rd, wr) == (fi["ntasks"], fi["hbm_read"], fi["hbm_written"])
+
+
+def test_share_rank_is_validated(hc):
+    c = hc.Comm(4, "int32")
+    assert _code(c.set_share, -2) == hc.ERR_INVALID_ARG
+    assert _code(c.set_share, 4) == hc.ERR_INVALID_ARG
+    c.set_share(3)
+    c.set_share(-1)
+    c.close()
