@@ -456,18 +456,24 @@ __device__ __forceinline__ void reduce_bf16_k(const DevTask* t, uint64_t e0, uin
   }
 }
 
-// fp8 payload with K (2..4) operands known at compile time: all K code
-// vectors and block scales of U 256-element blocks per lane group are
-// loaded before the arithmetic starts. Same dequantize / sum / rescale /
-// encode steps as reduce_fp8, with gfx950's packed OCP e4m3 conversions:
-// decoding is exact, and encoding rounds to nearest even; after rescaling
-// every value lies within +-448, so saturation never applies. The GPU
-// parity tests check the results bit for bit against the oracle's
-// software codec.
+// fp8 payload with K (2..4) operands known at compile time. Each wave owns
+// a run of 32 whole 256-element blocks per pass (U = 8 vectors per lane, 64
+// lanes), so the blocks' scales form one 128-byte line per operand: lanes
+// 0..31 fetch it with a single load and, at the end of the pass, write the
+// new scales back as one full line. (Per-block 4-byte scale stores from
+// scattered lanes were partial-line writes and cost about a tenth of the
+// kernel's time.) Every code vector of the pass is loaded before the
+// arithmetic starts. Same dequantize / sum / rescale / encode steps as
+// reduce_fp8, with gfx950's packed OCP e4m3 conversions: decoding is exact,
+// and encoding rounds to nearest even; after rescaling every value lies
+// within +-448, so saturation never applies. The GPU parity tests check the
+// results bit for bit against the oracle's software codec.
 template <int BLOCK, int K>
 __device__ __forceinline__ void reduce_fp8_k(const DevTask* t, uint64_t e0, uint64_t n) {
   constexpr int U = 8;                           // vectors per lane in flight (measured best)
-  const uint32_t tid = threadIdx.x;
+  constexpr uint32_t kWave = U * 64;             // vectors per wave and pass: 32 blocks
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = uni32(threadIdx.x >> 6);
   const rsrc_t rd = rsrc(uni64(t->dst) + e0, n);
   const rsrc_t rdsc = rsrc(uni64(t->dst_sc) + (e0 / 256) * 4, (n / 256) * 4);
   rsrc_t rs[K], rsc[K];
@@ -477,34 +483,29 @@ __device__ __forceinline__ void reduce_fp8_k(const DevTask* t, uint64_t e0, uint
     rsc[j] = rsrc(src_sc_addr(t, j, K) + (e0 / 256) * 4, (n / 256) * 4);
   }
   const uint32_t nv = uint32_t(n >> 4);          // 16-code vectors; whole 256-code blocks
-  const uint32_t nv_round = (nv + U * BLOCK - 1) / (U * BLOCK) * (U * BLOCK);
-  for (uint32_t i = tid; i < nv_round; i += U * BLOCK) {
+  const uint32_t nblk = nv >> 4;
+  for (uint32_t base = wave * kWave; base < nv; base += (BLOCK / 64) * kWave) {
+    const uint32_t blk0 = base >> 4;
+    const bool own = lane < 32u && blk0 + lane < nblk;   // lane L carries block blk0 + L's scales
+    uint32_t scl[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) scl[j] = own ? ld4(rsc[j], (blk0 + lane) * 4u) : 0u;
     uint4 w[U][K];
-    uint32_t sc[U][K];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t iv = i + u * BLOCK;
-      if (iv < nv) {
+      const uint32_t iv = base + u * 64u + lane;
 #pragma unroll
-        for (int j = 0; j < K; ++j) {
-          w[u][j] = ld16(rs[j], iv * 16u);
-          sc[u][j] = ld4(rsc[j], (iv >> 4) * 4u);
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-          w[u][j] = make_uint4(0, 0, 0, 0);
-          sc[u][j] = 0;
-        }
-      }
+      for (int j = 0; j < K; ++j) w[u][j] = iv < nv ? ld16(rs[j], iv * 16u) : make_uint4(0, 0, 0, 0);
     }
+    uint32_t nsc = 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const uint32_t iv = i + u * BLOCK;
+      const uint32_t iv = base + u * 64u + lane;
+      const int from = int(u * 4u + (lane >> 4)) * 4;    // the lane carrying this vector's block
       float a[16];
 #pragma unroll
       for (int j = 0; j < K; ++j) {
-        const float s = __uint_as_float(sc[u][j]);
+        const float s = __uint_as_float(uint32_t(__builtin_amdgcn_ds_bpermute(from, int(scl[j]))));
         const uint32_t ws[4] = {w[u][j].x, w[u][j].y, w[u][j].z, w[u][j].w};
 #pragma unroll
         for (int wd = 0; wd < 4; ++wd) {
@@ -530,10 +531,33 @@ __device__ __forceinline__ void reduce_fp8_k(const DevTask* t, uint64_t e0, uint
           o[wd] = uint32_t(x);
         }
         st16(rd, iv * 16u, make_uint4(o[0], o[1], o[2], o[3]));
-        if ((iv & 15u) == 0) st4(rdsc, (iv >> 4) * 4u, __float_as_uint(amax == 0.f ? 1.f : ldexpf(1.f, e)));
       }
+      // block blk0 + L (L = 4u + r) was rescaled by row r of this step: lane L takes it
+      const uint32_t sv = __float_as_uint(amax == 0.f ? 1.f : ldexpf(1.f, e));
+      const uint32_t g = uint32_t(__builtin_amdgcn_ds_bpermute(int((lane & 3u) * 16u) * 4, int(sv)));
+      if ((lane >> 2) == u) nsc = g;
     }
+    if (own) st4(rdsc, (blk0 + lane) * 4u, nsc);
   }
+}
+
+// fp8 copy: codes and block scales. The scales' loads (one dword per lane)
+// go out before the codes' copy, so they complete under it instead of
+// adding a dependent round trip after it.
+template <int BLOCK>
+__device__ __forceinline__ void copy_fp8(const DevTask* t, uint64_t e0, uint64_t n) {
+  const uint32_t tid = threadIdx.x;
+  const uint64_t ssc = uni64(t->src_sc[0]) + (e0 / 256) * 4, dsc = uni64(t->dst_sc) + (e0 / 256) * 4;
+  const uint32_t nsw = uint32_t(n / 256);        // scale words of the tile
+  const bool one = nsw <= uint32_t(BLOCK);
+  const rsrc_t rss = rsrc(ssc, uint64_t(nsw) * 4), rds = rsrc(dsc, uint64_t(nsw) * 4);
+  uint32_t v = 0;
+  if (one && tid < nsw) v = ld4(rss, tid * 4u);
+  copy_bytes<BLOCK>(uni64(t->src[0]) + e0, uni64(t->dst) + e0, n);
+  if (!one)
+    copy_bytes<BLOCK>(ssc, dsc, uint64_t(nsw) * 4);
+  else if (tid < nsw)
+    st4(rds, tid * 4u, v);
 }
 
 // NARROW = the table may hold bf16 / fp8 tasks; without it those paths are
@@ -549,9 +573,11 @@ __device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t
   const uint64_t n = e1 - e0;
   if (kind == kCopy) {
     const uint64_t es = dt == HICCL_BFLOAT16 ? 2 : (dt == HICCL_FP8_E4M3 ? 1 : 4);
+    if (NARROW && dt == HICCL_FP8_E4M3) {
+      copy_fp8<BLOCK>(t, e0, n);
+      return;
+    }
     copy_bytes<BLOCK>(uni64(t->src[0]) + e0 * es, uni64(t->dst) + e0 * es, n * es);
-    if (NARROW && dt == HICCL_FP8_E4M3)
-      copy_bytes<BLOCK>(uni64(t->src_sc[0]) + (e0 / 256) * 4, uni64(t->dst_sc) + (e0 / 256) * 4, (n / 256) * 4);
     return;
   }
   if (dt == HICCL_FLOAT32) {
