@@ -559,7 +559,9 @@ SERVE_HIERS = [[2, 4], [2, 4, 2], [4, 4]]
 
 def serve_bench(torch, ntemplates=48, nreq=2000, fractions=(0.25, 0.5, 0.75, 0.9, 1.2), slots=4,
                 budget=200 * 10 ** 9, seed=8, mode="persistent"):
-    """Poisson stream of collective requests over resident request templates.
+    """Poisson stream of collective requests over resident request templates, served three ways: one
+    launch per request on concurrent slots (continuous batching), the device request ring (one resident
+    launch serving the requests the host appends), and one request at a time (FIFO).
 
     Templates are drawn from the serving mix (type uniform over the six, hierarchy from {2x4, 2x4x2, 4x4},
     per-rank size log-uniform in [1 KiB, 256 MiB], dtype from {int32, float32, bf16}); each keeps its
@@ -589,8 +591,8 @@ def serve_bench(torch, ntemplates=48, nreq=2000, fractions=(0.25, 0.5, 0.75, 0.9
         temps.append({"comm": c, "snd": snd, "rcv": rcv, "S": S, "foot": foot, "name": name, "p": p})
     torch.cuda.synchronize()
 
-    def run_stream(arrivals, picks, nslots):
-        srv = Server(budget, nslots)
+    def run_stream(arrivals, picks, nslots, ring=False):
+        srv = Server(budget, nslots, ring=ring)
         busy = [False] * len(temps)
         queue, inflight, lat = [], {}, []
         t0 = time.perf_counter()
@@ -634,15 +636,20 @@ def serve_bench(torch, ntemplates=48, nreq=2000, fractions=(0.25, 0.5, 0.75, 0.9
     # closed loop: everything arrives at once -> sustained service rate mu
     span, _ = run_stream(np.zeros(nreq), picks, slots)
     mu = nreq / span
-    _progress(f"serve closed loop: {mu:.1f} requests/s")
+    ring_ok = mode == "persistent"          # the device ring serves persistent-executor templates
+    mu_ring = nreq / run_stream(np.zeros(nreq), picks, slots, ring=True)[0] if ring_ok else None
+    _progress(f"serve closed loop: {mu:.1f} requests/s (device ring: {mu_ring})")
     out = {"executor": mode, "templates": ntemplates, "requests_per_rate": nreq, "slots": slots, "budget_bytes": budget,
-           "mu_req_per_s": round(mu, 1), "rates": []}
+           "mu_req_per_s": round(mu, 1), "mu_ring_req_per_s": round(mu_ring, 1) if mu_ring else None, "rates": []}
     for f in fractions:
         lam = f * mu
         arrivals = np.cumsum(g.exponential(1.0 / lam, nreq))
         row = {"fraction_of_mu": f, "lambda_req_per_s": round(lam, 1)}
-        for label, ns in (("continuous", slots), ("fifo", 1)):
-            span, lat = run_stream(arrivals, picks, ns)
+        forms = (("continuous", slots, False), ("ring", slots, True), ("fifo", 1, False))
+        for label, ns, ring in forms:
+            if ring and not ring_ok:
+                continue
+            span, lat = run_stream(arrivals, picks, ns, ring)
             Sb = sum(temps[tp]["S"] for tp in picks)
             row[label] = {"throughput_req_per_s": round(nreq / span, 1), "algbw_GBps": round(Sb / span / 1e9, 2),
                           "latency_ms_p50": round(float(np.percentile(lat, 50)) * 1e3, 3),

@@ -353,6 +353,25 @@ int hiccl_server_poll(hiccl_server_t srv, uint64_t ticket, int* done, double* de
 int hiccl_server_drain(hiccl_server_t srv);
 /* Bytes currently charged and requests currently running. */
 int hiccl_server_usage(hiccl_server_t srv, size_t* used_bytes, int* running);
+/* Serve the following launches from a device request ring instead of one
+ * launch each. A resident launch of `grid` workgroups (0 = one per compute
+ * unit; otherwise at least 2) on a stream of its own serves the ring:
+ * workgroup 0 polls the ring's tail in host-coherent memory and publishes
+ * new requests to the others, which execute the requests in arrival order
+ * with the persistent executor's claim / wait / retire steps, one request's
+ * last tiles overlapping the next one's first. hiccl_server_launch then
+ * appends the communicator's uploaded table to the ring (it must use the
+ * persistent executor; UNSUPPORTED otherwise), and progress / poll read
+ * each request's completion word; device_us is 0 for these requests. The
+ * resident launch exits after `idle_ms` (1..60000) without a new request,
+ * and a later launch starts it again; while it runs, a device-wide
+ * synchronization (hipDeviceSynchronize) waits for it to go idle. A
+ * communicator must not run elsewhere while it is in the ring. The ring
+ * holds 4096 entries; HICCL_ERR_STATE if requests are in flight or the ring
+ * is already started. hiccl_server_destroy stops the ring after it has
+ * served what was appended (bounded wait: TIMEOUT, with nothing freed, if
+ * the resident launch does not stop within 30 s). */
+int hiccl_server_start_ring(hiccl_server_t srv, int grid, int idle_ms);
 int hiccl_server_destroy(hiccl_server_t srv);
 
 /* --------------------------------------------------------- payload formats */

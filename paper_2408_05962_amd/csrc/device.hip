@@ -17,7 +17,11 @@
 #include <array>
 #include <cmath>
 #include <numeric>
+#include <chrono>
 #include <cstdio>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 
 #include "hiccl_impl.hpp"
 
@@ -864,6 +868,185 @@ __global__ __launch_bounds__(BLOCK) void hiccl_staged(ExecArgs a, uint32_t lo, u
   }
 }
 
+// ------------------------------------------------------ device request ring
+// The serving form's resident executor. The host appends requests (each an
+// uploaded communicator's ExecArgs) to a ring in host-coherent memory and
+// advances its tail; one resident launch serves them in arrival order.
+// Workgroup 0 is the dispatcher: it polls the host tail, copies each new
+// entry into a device-memory ring and publishes the device tail. Every other
+// workgroup is a worker that takes the requests in order: it claims a
+// request's tiles one at a time from the request's claim counter (table
+// order, which is topological), waits for the tile's predecessors (bounded),
+// runs the tile and retires it. Once a request has no unclaimed tile the
+// worker leaves for the next one, so one request's last tiles overlap the
+// next request's first. The last worker to leave a request resets the
+// request's counters and writes its completion word to host memory, with
+// the abort bit set if a dependency wait expired.
+//
+// Exit: the dispatcher stops when the host sets stop, or after `idle_limit`
+// polls that found no new request. It first publishes the device tail it
+// has reached, then the stop epoch; workers serve every request below that
+// tail before they leave, so the grid always drains. The dispatcher reports
+// the position it stopped at to the host, which starts a new instance from
+// there (on the same stream, after this one) when requests are pending.
+struct RingShared {                  // host-coherent memory
+  uint32_t tail;                     // host: requests appended
+  uint32_t stop;                     // host: serve what is appended, then exit
+  uint32_t exit_pos, exit_epoch;     // device: where an instance stopped, and which
+};
+struct RingArgs {
+  RingShared* host;
+  const ExecArgs* host_entry;        // [cap], host-coherent
+  uint32_t* host_done;               // [cap], host-coherent: position + 1, bit 31 = aborted
+  uint32_t* dev_tail;                // device memory, 128-byte line each
+  uint32_t* dev_stop;
+  ExecArgs* dev_entry;               // [cap]
+  uint32_t* dev_left;                // [cap] workers that have left the request
+  uint32_t cap, epoch, start, idle_limit;
+};
+constexpr uint32_t kRingAborted = 0x80000000u;
+static_assert(sizeof(ExecArgs) % 16 == 0, "ring entries are copied in 16-byte pieces");
+
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void hiccl_ring(RingArgs r) {
+  constexpr uint32_t kPieces = sizeof(ExecArgs) / 16;
+  __shared__ ExecArgs s_args;
+  __shared__ DevTask s_task;
+  __shared__ uint32_t s_word[2];
+  const uint32_t tid = threadIdx.x;
+  const bool lead = tid == 0;
+  if (blockIdx.x == 0) {
+    // dispatcher
+    uint32_t pos = r.start, idle = 0;
+    for (;;) {
+      if (lead) {
+        // stop first: the host sets it after its last tail, so a tail read after it is final
+        const uint32_t stop = __hip_atomic_load(&r.host->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        const uint32_t tail = __hip_atomic_load(&r.host->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        s_word[0] = tail;
+        s_word[1] = stop;
+      }
+      __syncthreads();
+      const uint32_t tail = __builtin_amdgcn_readfirstlane(s_word[0]);
+      const bool stop = __builtin_amdgcn_readfirstlane(s_word[1]) != 0;
+      __syncthreads();
+      if (tail != pos) {
+        constexpr uint32_t kWords = sizeof(ExecArgs) / 4;
+        const uint32_t n = tail - pos;
+        for (uint32_t i = tid; i < n * kWords; i += BLOCK) {
+          const uint32_t e = (pos + i / kWords) % r.cap, w = i % kWords;
+          const uint32_t v = __hip_atomic_load(reinterpret_cast<const uint32_t*>(r.host_entry + e) + w,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+          st4(rsrc(uint64_t(reinterpret_cast<uintptr_t>(r.dev_entry + e)), sizeof(ExecArgs)), w * 4u, v);
+        }
+        wait_mem();
+        __syncthreads();
+        if (lead) __hip_atomic_store(r.dev_tail, tail, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        pos = tail;
+        idle = 0;
+        continue;
+      }
+      if (stop || ++idle >= r.idle_limit) break;
+      __builtin_amdgcn_s_sleep(127);
+    }
+    if (lead) {
+      __hip_atomic_store(r.dev_stop, r.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&r.host->exit_pos, pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&r.host->exit_epoch, r.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    return;
+  }
+  // worker
+  const uint32_t workers = gridDim.x - 1;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid) / 64;
+  const uint32_t lane = tid & 63u;
+  for (uint32_t pos = r.start;; ++pos) {
+    if (lead) {
+      uint32_t have = 0;
+      for (;;) {
+        if (__hip_atomic_load(r.dev_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != pos) {
+          have = 1;
+          break;
+        }
+        if (__hip_atomic_load(r.dev_stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == r.epoch) {
+          // the dispatcher published its final tail before the stop epoch
+          have = __hip_atomic_load(r.dev_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != pos;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(8);
+      }
+      s_word[0] = have;
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_word[0]) == 0) break;
+    const uint32_t e = pos % r.cap;
+    if (tid < kPieces)
+      reinterpret_cast<uint4*>(&s_args)[tid] =
+          ld16(rsrc(uint64_t(reinterpret_cast<uintptr_t>(r.dev_entry + e)), sizeof(ExecArgs)), tid * 16u);
+    __syncthreads();
+    const ExecArgs a = s_args;
+    for (;;) {
+      if (wave == 0) {
+        uint32_t tl_l = kNoTile;
+        if (lead) {
+          const uint32_t c = __hip_atomic_fetch_add(&a.ctl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (c < a.ntiles && !__hip_atomic_load(&a.ctl[CTL_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            tl_l = c;
+        }
+        uint32_t tl = __builtin_amdgcn_readfirstlane(tl_l);
+        if (tl != kNoTile) {
+          const uint32_t k = __builtin_amdgcn_readfirstlane(a.tile_task[tl]);
+          stage_desc(&s_task, a.tasks + k, lane);
+          __builtin_amdgcn_s_waitcnt(0);
+          if (lead && !wait_ready(a, k, s_task.npred)) tl = kNoTile;
+          if (lead) s_word[0] = k;
+        }
+        if (lead) s_word[1] = tl;
+      }
+      __syncthreads();
+      const uint32_t tl = __builtin_amdgcn_readfirstlane(s_word[1]);
+      if (tl == kNoTile) break;
+      run_tile<BLOCK, true>(&s_task, tl);
+      wait_mem();
+      __syncthreads();
+      if (lead) retire(a, ref_of(s_task, s_word[0]));
+      __syncthreads();
+    }
+    __syncthreads();   // every wave has read the final claim word before it is reused
+    // leave the request; the last worker out resets it and reports completion
+    if (lead) {
+      const uint32_t old = __hip_atomic_fetch_add(&r.dev_left[e], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      s_word[0] = old + 1 == workers;
+      s_word[1] = __hip_atomic_load(&a.ctl[CTL_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_word[0])) {
+      const bool aborted = __builtin_amdgcn_readfirstlane(s_word[1]) != 0;
+      // no kernel boundary follows: the resets are device-coherent stores
+      auto put = [](uint32_t* at, uint32_t v) { __hip_atomic_store(at, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+      for (uint32_t i = tid; i < a.ntasks; i += BLOCK) {
+        put(&a.pending[i], 0);
+        put(&a.done[i], 0);
+      }
+      for (uint32_t i = tid; i < a.ncomm; i += BLOCK) put(&a.comm_left[i], a.comm_ntasks[i]);
+      if (tid < kMaxQueues) put(&a.ctl[tid * kLine], 0);
+      if (lead) {
+        put(&a.ctl[CTL_ABORT], 0);
+        put(&a.ctl[CTL_EXIT], 0);
+        put(&a.ctl[CTL_STATUS], 0);
+      }
+      wait_mem();
+      __syncthreads();
+      if (lead) {
+        put(&r.dev_left[e], 0);
+        __hip_atomic_store(&r.host_done[e], (pos + 1) | (aborted ? kRingAborted : 0u), __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 constexpr int kBlock = 256;
 constexpr int kGraphBranches = 4;     // parallel branches of the captured batch graph
 
@@ -933,14 +1116,22 @@ struct DeviceState {
   hipEvent_t ev = nullptr;
   hipStream_t last_stream = nullptr;
   bool launched = false;
+  uint64_t ring_id = 0;                // device request ring holding this table's latest request (0: none)
+  uint32_t ring_pos = 0;               // that request's position
 };
 
 void device_state_set_spin_limit(DeviceState* s, uint32_t polls) {
   if (s) s->exe.spin_limit = polls;
 }
 
+// A table that a device-ring request still uses must not be freed or run
+// elsewhere (device request ring, end of this file).
+static bool ring_request_pending(uint64_t ring_id, uint32_t pos);
+static void ring_request_wait(uint64_t ring_id, uint32_t pos);
+
 void device_state_free(DeviceState* s) {
   if (!s) return;
+  if (s->ring_id) ring_request_wait(s->ring_id, s->ring_pos);
   s->exe.free_all();
   if (s->own_ws && s->ws) (void)hipFree(s->ws);
   if (s->ev) (void)hipEventDestroy(s->ev);
@@ -1177,6 +1368,8 @@ int hiccl_run(hiccl_comm_t comm, void* stream) {
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   if (c.dev && c.dev->launched && c.dev->last_stream != st && hipEventQuery(c.dev->ev) == hipErrorNotReady)
     return fail(HICCL_ERR_STATE, "a run of this communicator is in flight on another stream");
+  if (c.dev && c.dev->ring_id && ring_request_pending(c.dev->ring_id, c.dev->ring_pos))
+    return fail(HICCL_ERR_STATE, "this communicator has a request in a device ring");
   if (int rc = ensure_device(c)) return rc;
   if (int rc = launch(c.dev->exe, st)) return rc;
   HIP_TRY(hipEventRecord(c.dev->ev, st));
@@ -1765,3 +1958,194 @@ int hiccl_from_payload(int dtype, const void* in, const float* scales, float* ou
 }
 
 }  // extern "C"
+
+// ===================================================== device request ring
+namespace hiccl {
+
+struct DeviceRing {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* host_block = nullptr;        // host-coherent: RingShared | entries | completion words
+  void* dev_block = nullptr;         // device: tail line | stop line | entries | leave counters
+  RingShared* shared = nullptr;
+  ExecArgs* host_entry = nullptr;
+  uint32_t* host_done = nullptr;
+  RingArgs args{};
+  uint32_t cap = 0, grid = 0, idle_limit = 0;
+  uint32_t next = 0;                 // positions appended
+  uint32_t resume = 0;               // where the next instance starts
+  uint32_t epoch = 0;
+  bool running = false;
+  uint64_t id = 0;                   // unique per ring of the process
+};
+
+static constexpr size_t kRingLine = 128;
+
+static std::mutex g_ring_mu;                                    // live rings by id
+static std::unordered_map<uint64_t, DeviceRing*> g_rings;
+
+// Whether the request at `pos` of ring `ring_id` has yet to finish. (An
+// entry is reused only after its request finished, so a request more than
+// `cap` positions old has finished; a destroyed ring served everything.)
+static bool pending_in(const DeviceRing* r, uint32_t pos);
+static bool ring_request_pending(uint64_t ring_id, uint32_t pos) {
+  std::lock_guard<std::mutex> g(g_ring_mu);
+  auto it = g_rings.find(ring_id);
+  return it != g_rings.end() && pending_in(it->second, pos);
+}
+
+// Start an instance if requests are pending and none runs; an instance that
+// has exited (stop or idle) hands over the position it stopped at.
+static int ring_keep_alive(DeviceRing* r) {
+  if (r->running && __atomic_load_n(&r->shared->exit_epoch, __ATOMIC_ACQUIRE) == r->epoch) {
+    r->running = false;
+    r->resume = __atomic_load_n(&r->shared->exit_pos, __ATOMIC_ACQUIRE);
+  }
+  if (r->running || r->resume == r->next) return HICCL_SUCCESS;
+  RingArgs a = r->args;
+  a.epoch = ++r->epoch;
+  a.start = r->resume;
+  hipLaunchKernelGGL(hiccl_ring<kBlock>, dim3(r->grid), dim3(kBlock), 0, r->stream, a);
+  HIP_TRY(hipGetLastError());
+  r->running = true;
+  return HICCL_SUCCESS;
+}
+
+static bool pending_in(const DeviceRing* r, uint32_t pos) {
+  return r->next - pos <= r->cap &&
+         (__atomic_load_n(&r->host_done[pos % r->cap], __ATOMIC_ACQUIRE) & ~kRingAborted) != pos + 1;
+}
+
+// Bounded wait (30 s) for a ring request before its table is freed; an idle
+// ring is started again for it.
+static void ring_request_wait(uint64_t ring_id, uint32_t pos) {
+  for (int i = 0; i < 30000; ++i) {
+    {
+      std::lock_guard<std::mutex> g(g_ring_mu);
+      auto it = g_rings.find(ring_id);
+      if (it == g_rings.end() || !pending_in(it->second, pos)) return;
+      (void)ring_keep_alive(it->second);
+    }
+    std::this_thread::sleep_for(std::chrono::milliseconds(1));
+  }
+}
+
+int ring_create(int grid, uint32_t idle_ms, uint32_t cap, DeviceRing** out) {
+  auto* r = new DeviceRing;
+  if (hipGetDevice(&r->device) != hipSuccess) {
+    delete r;
+    return fail(HICCL_ERR_HIP, "no current device");
+  }
+  static std::atomic<uint64_t> serial{0};
+  r->id = ++serial;
+  r->cap = cap;
+  r->grid = uint32_t(grid > 0 ? grid : cu_count());
+  if (r->grid < 2) r->grid = 2;                      // the dispatcher and at least one worker
+  // a dispatcher poll is a sleep of ~3.4 us plus a host-memory read of ~1-2 us
+  r->idle_limit = std::max<uint32_t>(1, idle_ms * 200u);
+  const size_t hbytes = kRingLine + cap * sizeof(ExecArgs) + cap * sizeof(uint32_t);
+  const size_t dbytes = 2 * kRingLine + cap * sizeof(ExecArgs) + cap * sizeof(uint32_t);
+  auto undo = [&](int rc) {
+    if (r->stream) (void)hipStreamDestroy(r->stream);
+    if (r->host_block) (void)hipHostFree(r->host_block);
+    if (r->dev_block) (void)hipFree(r->dev_block);
+    delete r;
+    return rc;
+  };
+  if (hipHostMalloc(&r->host_block, hbytes, hipHostMallocCoherent) != hipSuccess)
+    return undo(fail(HICCL_ERR_OOM, "ring: host-coherent allocation failed"));
+  if (hipMalloc(&r->dev_block, dbytes) != hipSuccess) return undo(fail(HICCL_ERR_OOM, "ring: device allocation failed"));
+  if (hipMemset(r->dev_block, 0, dbytes) != hipSuccess) return undo(fail(HICCL_ERR_HIP, "ring: clearing failed"));
+  if (hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking) != hipSuccess)
+    return undo(fail(HICCL_ERR_HIP, "ring: stream creation failed"));
+  std::memset(r->host_block, 0, hbytes);
+  auto* hb = static_cast<uint8_t*>(r->host_block);
+  r->shared = reinterpret_cast<RingShared*>(hb);
+  r->host_entry = reinterpret_cast<ExecArgs*>(hb + kRingLine);
+  r->host_done = reinterpret_cast<uint32_t*>(hb + kRingLine + cap * sizeof(ExecArgs));
+  void* hdev = nullptr;
+  if (hipHostGetDevicePointer(&hdev, r->host_block, 0) != hipSuccess)
+    return undo(fail(HICCL_ERR_HIP, "ring: no device address for host memory"));
+  auto* hd = static_cast<uint8_t*>(hdev);
+  auto* db = static_cast<uint8_t*>(r->dev_block);
+  RingArgs& a = r->args;
+  a.host = reinterpret_cast<RingShared*>(hd);
+  a.host_entry = reinterpret_cast<const ExecArgs*>(hd + kRingLine);
+  a.host_done = reinterpret_cast<uint32_t*>(hd + kRingLine + cap * sizeof(ExecArgs));
+  a.dev_tail = reinterpret_cast<uint32_t*>(db);
+  a.dev_stop = reinterpret_cast<uint32_t*>(db + kRingLine);
+  a.dev_entry = reinterpret_cast<ExecArgs*>(db + 2 * kRingLine);
+  a.dev_left = reinterpret_cast<uint32_t*>(db + 2 * kRingLine + cap * sizeof(ExecArgs));
+  a.cap = cap;
+  a.idle_limit = r->idle_limit;
+  {
+    std::lock_guard<std::mutex> g(g_ring_mu);
+    g_rings[r->id] = r;
+  }
+  *out = r;
+  return HICCL_SUCCESS;
+}
+
+int ring_push(DeviceRing* r, Comm& c, uint32_t* pos) {
+  if (!c.planned) return fail(HICCL_ERR_STATE, "call hiccl_init first");
+  if (c.exec.mode != HICCL_EXEC_PERSISTENT)
+    return fail(HICCL_ERR_UNSUPPORTED, "the device ring serves persistent-executor communicators");
+  if (hipSetDevice(r->device) != hipSuccess) return fail(HICCL_ERR_HIP, "ring: cannot select its device");
+  if (int rc = ensure_device(c)) return rc;
+  if (c.dev->launched && hipEventQuery(c.dev->ev) == hipErrorNotReady)
+    return fail(HICCL_ERR_STATE, "a run of this communicator is in flight");
+  if (c.dev->ring_id && ring_request_pending(c.dev->ring_id, c.dev->ring_pos))
+    return fail(HICCL_ERR_STATE, "this communicator's previous request is still in a device ring");
+  const uint32_t p = r->next, e = p % r->cap;
+  if (p >= (1u << 31)) return fail(HICCL_ERR_UNSUPPORTED, "ring positions exhausted");
+  if (p >= r->cap && (__atomic_load_n(&r->host_done[e], __ATOMIC_ACQUIRE) & ~kRingAborted) != p - r->cap + 1)
+    return fail(HICCL_ERR_BUSY, "ring entry still in use");
+  __atomic_store_n(&r->host_done[e], 0u, __ATOMIC_RELAXED);
+  r->host_entry[e] = c.dev->exe.args();
+  std::atomic_thread_fence(std::memory_order_release);
+  __atomic_store_n(&r->shared->tail, p + 1, __ATOMIC_RELEASE);
+  r->next = p + 1;
+  *pos = p;
+  c.dev->ring_id = r->id;
+  c.dev->ring_pos = p;
+  return ring_keep_alive(r);
+}
+
+// Completion of the request at position pos: done = 1 once its last worker
+// has left it; aborted = 1 if one of its dependency waits expired.
+int ring_check(DeviceRing* r, uint32_t pos, int* done, int* aborted) {
+  if (int rc = ring_keep_alive(r)) return rc;
+  const uint32_t w = __atomic_load_n(&r->host_done[pos % r->cap], __ATOMIC_ACQUIRE);
+  *done = (w & ~kRingAborted) == pos + 1;
+  *aborted = *done && (w & kRingAborted) != 0;
+  return HICCL_SUCCESS;
+}
+
+// Stop: the running instance serves what is appended, then exits. The wait
+// for it is bounded; past the bound the ring's memory is left allocated
+// (a kernel may still use it) and the call reports a timeout.
+int ring_destroy(DeviceRing* r) {
+  if (!r) return HICCL_SUCCESS;
+  (void)hipSetDevice(r->device);
+  __atomic_store_n(&r->shared->stop, 1u, __ATOMIC_RELEASE);
+  int rc = ring_keep_alive(r);
+  for (int i = 0; rc == HICCL_SUCCESS; ++i) {
+    const hipError_t q = hipStreamQuery(r->stream);
+    if (q == hipSuccess) break;
+    if (q != hipErrorNotReady) rc = fail(HICCL_ERR_HIP, std::string("ring: ") + hipGetErrorString(q));
+    else if (i >= 30000) rc = fail(HICCL_ERR_TIMEOUT, "ring: the resident kernel did not stop within 30 s");
+    else std::this_thread::sleep_for(std::chrono::milliseconds(1));
+  }
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> g(g_ring_mu);
+    g_rings.erase(r->id);
+  }
+  (void)hipStreamDestroy(r->stream);
+  (void)hipHostFree(r->host_block);
+  (void)hipFree(r->dev_block);
+  delete r;
+  return HICCL_SUCCESS;
+}
+
+}  // namespace hiccl

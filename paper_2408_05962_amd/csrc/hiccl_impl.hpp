@@ -141,6 +141,14 @@ struct Comm {
 void set_error(const std::string& msg);
 int fail(int code, const std::string& msg);
 
+// Device request ring of the serving form (device.hip). A resident launch
+// serves appended requests in order; positions count appended requests.
+struct DeviceRing;
+int ring_create(int grid, uint32_t idle_ms, uint32_t cap, DeviceRing** out);
+int ring_push(DeviceRing* r, Comm& c, uint32_t* pos);
+int ring_check(DeviceRing* r, uint32_t pos, int* done, int* aborted);
+int ring_destroy(DeviceRing* r);
+
 // plan.cpp
 int build_plan(Comm& c);
 void order_and_tile(Plan& p, int order, size_t tile_bytes);

@@ -1,10 +1,14 @@
 // Serving loop support: admission under a device-memory budget and a fixed
-// number of concurrent slots (one stream each), so that requests arriving
-// while others execute are admitted as soon as a slot and budget free up
-// and their work overlaps on the device (continuous batching).
+// number of concurrent slots, so that requests arriving while others execute
+// are admitted as soon as a slot and budget free up and their work overlaps
+// on the device (continuous batching). A request runs either as its own
+// launch on its slot's stream, or, once the server has started its device
+// request ring, as an entry of that ring served by one resident launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -21,6 +25,7 @@ struct hiccl_server_s {
     double device_us = 0;
     hiccl_comm_t comm = nullptr;        // the launched communicator
     int status = HICCL_SUCCESS;         // its run's outcome once done
+    uint32_t ring_pos = 0;              // device ring: the request's position
   };
   size_t budget = 0, used = 0;
   std::vector<hipStream_t> streams;
@@ -28,6 +33,7 @@ struct hiccl_server_s {
   std::unordered_map<uint64_t, Req> reqs;
   uint64_t next = 1;
   int share_grid = 0;                  // workgroups of a request that runs beside others
+  DeviceRing* ring = nullptr;          // set: requests go to the device request ring
 };
 
 #define HIP_OK(expr, what)                                                         \
@@ -119,6 +125,12 @@ int hiccl_server_launch(hiccl_server_t s, uint64_t ticket, hiccl_comm_t comm) {
     s->reqs.erase(it);
     return rc;
   };
+  if (s->ring) {
+    if (int rc = ring_push(s->ring, comm->c, &r.ring_pos)) return give_up(rc);
+    r.launched = true;
+    r.comm = comm;
+    return HICCL_SUCCESS;
+  }
   if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess ||
       hipEventRecord(r.start, st) != hipSuccess)
     return give_up(fail(HICCL_ERR_HIP, "request events"));
@@ -134,6 +146,15 @@ int hiccl_server_progress(hiccl_server_t s) {
   for (auto& kv : s->reqs) {
     auto& r = kv.second;
     if (!r.launched || r.done) continue;
+    if (s->ring) {
+      int done = 0, aborted = 0;
+      if (int rc = ring_check(s->ring, r.ring_pos, &done, &aborted)) return rc;
+      if (!done) continue;
+      r.status = aborted ? HICCL_ERR_TIMEOUT : HICCL_SUCCESS;
+      r.done = true;
+      release(s, kv.first, r);
+      continue;
+    }
     hipError_t q = hipEventQuery(r.stop);
     if (q == hipErrorNotReady) continue;
     if (q != hipSuccess) return fail(HICCL_ERR_HIP, std::string("request failed: ") + hipGetErrorString(q));
@@ -168,7 +189,26 @@ int hiccl_server_poll(hiccl_server_t s, uint64_t ticket, int* done, double* devi
 int hiccl_server_drain(hiccl_server_t s) {
   if (!s) return fail(HICCL_ERR_INVALID_ARG, "NULL server");
   for (hipStream_t st : s->streams) HIP_OK(hipStreamSynchronize(st), "stream sync");
-  return hiccl_server_progress(s);
+  if (!s->ring) return hiccl_server_progress(s);
+  // ring requests: poll their completion words (a dependency wait is bounded, so they finish)
+  for (int i = 0;; ++i) {
+    if (int rc = hiccl_server_progress(s)) return rc;
+    bool pending = false;
+    for (const auto& kv : s->reqs) pending |= kv.second.launched && !kv.second.done;
+    if (!pending) return HICCL_SUCCESS;
+    if (i >= 600000) return fail(HICCL_ERR_TIMEOUT, "ring requests did not complete within 60 s");
+    std::this_thread::sleep_for(std::chrono::microseconds(100));
+  }
+}
+
+int hiccl_server_start_ring(hiccl_server_t s, int grid, int idle_ms) {
+  if (!s) return fail(HICCL_ERR_INVALID_ARG, "NULL server");
+  if (grid < 0 || grid == 1 || idle_ms < 1 || idle_ms > 60000)
+    return fail(HICCL_ERR_INVALID_ARG, "ring grid must be 0 or >= 2, idle time 1..60000 ms");
+  if (s->ring) return fail(HICCL_ERR_STATE, "the device ring is already started");
+  for (const auto& kv : s->reqs)
+    if (kv.second.launched && !kv.second.done) return fail(HICCL_ERR_STATE, "requests are in flight");
+  return ring_create(grid, uint32_t(idle_ms), 4096, &s->ring);
 }
 
 int hiccl_server_usage(hiccl_server_t s, size_t* used_bytes, int* running) {
@@ -184,6 +224,10 @@ int hiccl_server_usage(hiccl_server_t s, size_t* used_bytes, int* running) {
 
 int hiccl_server_destroy(hiccl_server_t s) {
   if (!s) return HICCL_SUCCESS;
+  if (s->ring) {
+    if (int rc = ring_destroy(s->ring)) return rc;   // the resident kernel did not stop: keep everything
+    s->ring = nullptr;
+  }
   for (hipStream_t st : s->streams) {
     (void)hipStreamSynchronize(st);
     (void)hipStreamDestroy(st);

@@ -7,8 +7,10 @@ addresses; torch tensors and numpy arrays are accepted and converted with
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("HICCL_LIB") or os.path.join(HERE, "libhiccl.so")
@@ -104,6 +106,7 @@ def lib():
             "hiccl_server_poll": [vp, u64, pi, C.POINTER(C.c_double)],
             "hiccl_server_drain": [vp],
             "hiccl_server_usage": [vp, C.POINTER(sz), pi],
+            "hiccl_server_start_ring": [vp, i, i],
             "hiccl_server_destroy": [vp],
             "hiccl_to_payload": [i, vp, vp, vp, sz, vp],
             "hiccl_from_payload": [i, vp, vp, vp, sz, vp],
@@ -338,13 +341,27 @@ def autotune_model(comm: Comm, stripes, pipes, tiles, reps=3, anchors=4, top=2, 
     return {"stripe": bs.value, "pipeline": bp.value, "tile_bytes": bt.value, "us": us.value, "measured": nm.value}
 
 
-class Server:
-    """Admission under a device-memory budget with concurrent slots."""
+_live_servers: "weakref.WeakSet[Server]" = weakref.WeakSet()
 
-    def __init__(self, hbm_budget: int, slots: int):
+
+@atexit.register
+def _close_servers():
+    # a server's device ring keeps a resident launch: stop it before the process ends
+    for s in list(_live_servers):
+        s.close()
+
+
+class Server:
+    """Admission under a device-memory budget with concurrent slots; with ``ring=True`` the
+    requests are served by a resident launch from a device request ring."""
+
+    def __init__(self, hbm_budget: int, slots: int, ring: bool = False, ring_grid: int = 0, idle_ms: int = 200):
         h = C.c_void_p()
         check(lib().hiccl_server_create(int(hbm_budget), int(slots), C.byref(h)))
         self.h = h
+        _live_servers.add(self)
+        if ring:
+            check(lib().hiccl_server_start_ring(self.h, int(ring_grid), int(idle_ms)))
 
     def admit(self, footprint: int):
         """A ticket, or None when the request must wait (no slot or budget free now)."""
@@ -381,7 +398,7 @@ class Server:
 
     def close(self):
         if getattr(self, "h", None):
-            lib().hiccl_server_destroy(self.h)
+            check(lib().hiccl_server_destroy(self.h))
             self.h = None
 
     def __del__(self):
