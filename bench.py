@@ -557,20 +557,13 @@ def precision_bench(torch, reps=5, n=1 << 28, sample_blocks=64):
 SERVE_HIERS = [[2, 4], [2, 4, 2], [4, 4]]
 
 
-def serve_bench(torch, ntemplates=48, nreq=2000, fractions=(0.25, 0.5, 0.75, 0.9, 1.2), slots=4,
-                budget=200 * 10 ** 9, seed=8, mode="persistent"):
-    """Poisson stream of collective requests over resident request templates, served three ways: one
-    launch per request on concurrent slots (continuous batching), the device request ring (one resident
-    launch serving the requests the host appends), and one request at a time (FIFO).
-
-    Templates are drawn from the serving mix (type uniform over the six, hierarchy from {2x4, 2x4x2, 4x4},
-    per-rank size log-uniform in [1 KiB, 256 MiB], dtype from {int32, float32, bf16}); each keeps its
-    buffers and schedule resident. A request picks a template; it is admitted when a slot and budget are
-    free and its template is idle. Latency = arrival to completion (host clock)."""
+def serve_templates(torch, ntemplates=48, seed=8, mode="persistent"):
+    """Resident request templates of the serving mix: type uniform over the six, hierarchy from {2x4, 2x4x2,
+    4x4}, per-rank size log-uniform in [1 KiB, 256 MiB], dtype from {int32, float32, bf16}. Each is run once
+    (buffers and schedule resident from then on)."""
     import numpy as np
 
     import synth
-    from paper_2408_05962_amd import Server
     from paper_2408_05962_amd import collectives as CO
     rng = synth.choice_stream(seed, 3)
     sizes = synth.log_uniform_sizes(seed, ntemplates, 1 << 10, 256 << 20, 16 * 16)
@@ -588,8 +581,27 @@ def serve_bench(torch, ntemplates=48, nreq=2000, fractions=(0.25, 0.5, 0.75, 0.9
         foot = snd.numel() * snd.element_size() + rcv.numel() * rcv.element_size() + c.workspace_size()
         c.run(torch.cuda.current_stream())
         c.wait()
-        temps.append({"comm": c, "snd": snd, "rcv": rcv, "S": S, "foot": foot, "name": name, "p": p})
+        temps.append({"comm": c, "snd": snd, "rcv": rcv, "S": S, "foot": foot, "name": name, "p": p, "h": h,
+                      "dtype": dtype, "stripe": s})
     torch.cuda.synchronize()
+    return temps
+
+
+def serve_bench(torch, ntemplates=48, nreq=2000, fractions=(0.25, 0.5, 0.75, 0.9, 1.2), slots=4,
+                budget=200 * 10 ** 9, seed=8, mode="persistent"):
+    """Poisson stream of collective requests over resident request templates, served three ways: one
+    launch per request on concurrent slots (continuous batching), the device request ring (one resident
+    launch serving the requests the host appends), and one request at a time (FIFO).
+
+    Templates are drawn from the serving mix (type uniform over the six, hierarchy from {2x4, 2x4x2, 4x4},
+    per-rank size log-uniform in [1 KiB, 256 MiB], dtype from {int32, float32, bf16}); each keeps its
+    buffers and schedule resident. A request picks a template; it is admitted when a slot and budget are
+    free and its template is idle. Latency = arrival to completion (host clock)."""
+    import numpy as np
+
+    import synth
+    from paper_2408_05962_amd import Server
+    temps = serve_templates(torch, ntemplates, seed, mode)
 
     def run_stream(arrivals, picks, nslots, ring=False):
         srv = Server(budget, nslots, ring=ring)

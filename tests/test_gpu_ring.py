@@ -157,3 +157,64 @@ def test_ring_argument_errors(torch_cuda):
     assert srv.usage() == (0, 0)                    # the failed launch released its ticket
     srv.close()
     c.close()
+
+
+@pytest.mark.timeout(400)
+def test_serving_mix_full_size_alone_and_in_the_mix(torch_cuda):
+    """The measured serving mix itself (the bench's 48 templates, up to 256 MiB per rank, int32 / float32 /
+    bf16): a stream of 300 requests served by the device ring, and again by concurrent slots, leaves every
+    requested template's result bit-identical to the template run alone. The alone results equal the oracle
+    for every int32 / float32 template up to 4 MiB per rank."""
+    torch = torch_cuda
+    import bench as B
+    import synth
+    from paper_2408_05962_amd import Server
+    temps = B.serve_templates(torch, 48, 8, "persistent")
+    st = torch.cuda.current_stream()
+    alone = []
+    for tp in temps:
+        tp["rcv"].zero_()
+        tp["comm"].run(st)
+        tp["comm"].wait()
+        alone.append(tp["rcv"].clone())
+    torch.cuda.synchronize()
+    for k, tp in enumerate(temps):
+        if tp["dtype"] == "bfloat16" or tp["S"] > 4 << 20:
+            continue
+        sends = list(tp["snd"].cpu().numpy())
+        out = alone[k].cpu().numpy()
+        ranks = [0] if tp["name"] == "reduce" else range(tp["p"])
+        H.check_result(tp["name"], {r: out[r] for r in ranks}, sends, tp["dtype"], h=tp["h"], s=tp["stripe"])
+    picks = [int(x) for x in synth.choice_stream(8, 4).integers(0, len(temps), 300)]
+    for ring in (True, False):
+        for tp in temps:
+            tp["rcv"].zero_()
+        st.synchronize()
+        srv = Server(200 * 10 ** 9, 4, ring=ring)
+        queue, inflight, busy = list(picks), {}, set()
+        t0 = time.time()
+        while queue or inflight:
+            assert time.time() - t0 < 120, "requests did not finish"
+            k = 0
+            while k < len(queue):
+                tpi = queue[k]
+                if tpi in busy:
+                    k += 1
+                    continue
+                tk = srv.admit(temps[tpi]["foot"])
+                if tk is None:
+                    break
+                srv.launch(tk, temps[tpi]["comm"])
+                busy.add(tpi)
+                inflight[tk] = tpi
+                queue.pop(k)
+            srv.progress()
+            for tk in list(inflight):
+                if srv.poll(tk)[0]:
+                    busy.discard(inflight.pop(tk))
+        srv.drain()
+        srv.close()
+        for k in sorted(set(picks)):
+            assert torch.equal(temps[k]["rcv"], alone[k]), (ring, k, temps[k]["name"], temps[k]["dtype"])
+    for tp in temps:
+        tp["comm"].close()
