@@ -422,19 +422,44 @@ def sweep_bench(torch):
         for _ in range(3):
             c.run(st)
         c.wait()
+        host = []
         for _ in range(50):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
             e0.record(st)
             c.run(st)
             e1.record(st)
+            c.wait()
+            host.append((time.perf_counter() - t0) * 1e6)
             torch.cuda.synchronize()
             lat.append(e0.elapsed_time(e1) * 1e3)
-        c.wait()
         ok = bool(torch.equal(rcv[0], snd.sum(0, dtype=torch.int32)) and torch.equal(rcv[3], rcv[0]))
         small[mode] = {"latency_us_p50": round(float(np.percentile(lat, 50)), 2),
-                       "latency_us_p99": round(float(np.percentile(lat, 99)), 2), "matches_sum": ok}
+                       "latency_us_p99": round(float(np.percentile(lat, 99)), 2), "matches_sum": ok,
+                       "host_us_p50": round(float(np.percentile(host, 50)), 2),
+                       "host_us_p99": round(float(np.percentile(host, 99)), 2)}
         c.close()
         del snd, rcv
+    # the same request through the device request ring: host clock from append to the completion word
+    from paper_2408_05962_amd import Server
+    c, snd, rcv = mk("all_reduce", [2, 2], 1, 1, "persistent", p=4, dd=65536 // 4, dtype="int32")
+    srv = Server(1 << 40, 1, ring=True, idle_ms=1000)
+    lat = []
+    for k in range(53):
+        t0 = time.perf_counter()
+        tk = srv.admit(1)
+        srv.launch(tk, c)
+        while not srv.poll(tk)[0]:
+            pass
+        if k >= 3:
+            lat.append((time.perf_counter() - t0) * 1e6)
+    srv.close()
+    ok = bool(torch.equal(rcv[0], snd.sum(0, dtype=torch.int32)) and torch.equal(rcv[3], rcv[0]))
+    small["device_ring"] = {"latency_us_p50": round(float(np.percentile(lat, 50)), 2),
+                            "latency_us_p99": round(float(np.percentile(lat, 99)), 2), "matches_sum": ok,
+                            "clock": "host, append to completion word"}
+    c.close()
+    del snd, rcv
     out["small_all_reduce_4r_2x2_int32_256KiB"] = small
     _progress(f"small all-reduce: {small}")
     return out

@@ -920,9 +920,12 @@ __global__ __launch_bounds__(BLOCK) void hiccl_ring(RingArgs r) {
     uint32_t pos = r.start, idle = 0;
     for (;;) {
       if (lead) {
-        // stop first: the host sets it after its last tail, so a tail read after it is final
-        const uint32_t stop = __hip_atomic_load(&r.host->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-        const uint32_t tail = __hip_atomic_load(&r.host->tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+        // stop first: the host sets it after its last tail, so a tail read after it is final. The
+        // polls are relaxed (an acquire here would invalidate this XCD's caches on every poll); the
+        // acquire fence runs once something changed.
+        const uint32_t stop = __hip_atomic_load(&r.host->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const uint32_t tail = __hip_atomic_load(&r.host->tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (stop || tail != pos) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
         s_word[0] = tail;
         s_word[1] = stop;
       }
@@ -962,19 +965,23 @@ __global__ __launch_bounds__(BLOCK) void hiccl_ring(RingArgs r) {
   const uint32_t lane = tid & 63u;
   for (uint32_t pos = r.start;; ++pos) {
     if (lead) {
+      // relaxed polls (an acquire invalidates this XCD's caches, which slows every workgroup on it);
+      // one acquire fence once the wait is over, before the request's tables are read
       uint32_t have = 0;
       for (;;) {
-        if (__hip_atomic_load(r.dev_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != pos) {
+        if (__hip_atomic_load(r.dev_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pos) {
           have = 1;
           break;
         }
-        if (__hip_atomic_load(r.dev_stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == r.epoch) {
+        if (__hip_atomic_load(r.dev_stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == r.epoch) {
           // the dispatcher published its final tail before the stop epoch
-          have = __hip_atomic_load(r.dev_tail, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != pos;
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          have = __hip_atomic_load(r.dev_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != pos;
           break;
         }
-        __builtin_amdgcn_s_sleep(8);
+        __builtin_amdgcn_s_sleep(16);
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       s_word[0] = have;
     }
     __syncthreads();
@@ -1013,9 +1020,12 @@ __global__ __launch_bounds__(BLOCK) void hiccl_ring(RingArgs r) {
       __syncthreads();
     }
     __syncthreads();   // every wave has read the final claim word before it is reused
-    // leave the request; the last worker out resets it and reports completion
+    // leave the request; the last worker out resets it and reports completion. As in retire(), a
+    // completed device-coherent access is already visible, so the count needs no cache maintenance:
+    // wait for this workgroup's last retire to complete, then count.
     if (lead) {
-      const uint32_t old = __hip_atomic_fetch_add(&r.dev_left[e], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      wait_mem();
+      const uint32_t old = __hip_atomic_fetch_add(&r.dev_left[e], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       s_word[0] = old + 1 == workers;
       s_word[1] = __hip_atomic_load(&a.ctl[CTL_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
