@@ -1991,6 +1991,18 @@ struct DeviceRing {
 
 static constexpr size_t kRingLine = 128;
 
+// Makes the ring's device current for a scope and restores the caller's.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
 static std::mutex g_ring_mu;                                    // live rings by id
 static std::unordered_map<uint64_t, DeviceRing*> g_rings;
 
@@ -2034,6 +2046,7 @@ static void ring_request_wait(uint64_t ring_id, uint32_t pos) {
       std::lock_guard<std::mutex> g(g_ring_mu);
       auto it = g_rings.find(ring_id);
       if (it == g_rings.end() || !pending_in(it->second, pos)) return;
+      DeviceGuard on(it->second->device);
       (void)ring_keep_alive(it->second);
     }
     std::this_thread::sleep_for(std::chrono::milliseconds(1));
@@ -2100,7 +2113,7 @@ int ring_push(DeviceRing* r, Comm& c, uint32_t* pos) {
   if (!c.planned) return fail(HICCL_ERR_STATE, "call hiccl_init first");
   if (c.exec.mode != HICCL_EXEC_PERSISTENT)
     return fail(HICCL_ERR_UNSUPPORTED, "the device ring serves persistent-executor communicators");
-  if (hipSetDevice(r->device) != hipSuccess) return fail(HICCL_ERR_HIP, "ring: cannot select its device");
+  DeviceGuard on(r->device);
   if (int rc = ensure_device(c)) return rc;
   if (c.dev->launched && hipEventQuery(c.dev->ev) == hipErrorNotReady)
     return fail(HICCL_ERR_STATE, "a run of this communicator is in flight");
@@ -2124,6 +2137,7 @@ int ring_push(DeviceRing* r, Comm& c, uint32_t* pos) {
 // Completion of the request at position pos: done = 1 once its last worker
 // has left it; aborted = 1 if one of its dependency waits expired.
 int ring_check(DeviceRing* r, uint32_t pos, int* done, int* aborted) {
+  DeviceGuard on(r->device);
   if (int rc = ring_keep_alive(r)) return rc;
   const uint32_t w = __atomic_load_n(&r->host_done[pos % r->cap], __ATOMIC_ACQUIRE);
   *done = (w & ~kRingAborted) == pos + 1;
@@ -2136,7 +2150,7 @@ int ring_check(DeviceRing* r, uint32_t pos, int* done, int* aborted) {
 // (a kernel may still use it) and the call reports a timeout.
 int ring_destroy(DeviceRing* r) {
   if (!r) return HICCL_SUCCESS;
-  (void)hipSetDevice(r->device);
+  DeviceGuard on(r->device);
   __atomic_store_n(&r->shared->stop, 1u, __ATOMIC_RELEASE);
   int rc = ring_keep_alive(r);
   for (int i = 0; rc == HICCL_SUCCESS; ++i) {
