@@ -700,19 +700,18 @@ def serve_bench(torch, ntemplates=48, nreq=2000, fractions=(0.25, 0.5, 0.75, 0.9
 
 def measured_traffic(mode, tile, grid):
     """HBM bytes per launch of the headline kernel from the committed rocprofv3 counter runs
-    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when they were taken on another
-    kernel source or launch configuration."""
-    import hashlib
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when they were taken on other kernel
+    code (the digest of the built kernels' instructions differs) or another launch configuration."""
     kname = "hiccl_staged" if mode == "staged" else "hiccl_persistent"
     path = os.path.join(ROOT, "profiles", f"traffic_{kname}_six_collectives_16r_64MiB.json")
-    src = os.path.join(ROOT, "paper_2408_05962_amd", "csrc", "device.hip")
-    if tile or grid or not os.path.exists(path) or not os.path.exists(src):
+    digest = os.path.join(ROOT, "paper_2408_05962_amd", "_build", "device_isa.sha256")
+    if tile or grid or not os.path.exists(path) or not os.path.exists(digest):
         return None
     with open(path) as f:
         rec = json.load(f)
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if rec.get("device_source_sha256") != sha or rec.get("mode") != mode:
+    with open(digest) as f:
+        isa = f.read().strip()
+    if rec.get("device_isa_sha256") != isa or rec.get("mode") != mode:
         return None
     return round(rec["traffic_bytes_per_launch"])
 

@@ -5,6 +5,7 @@ code (csrc/*.hip). Run ``python -m paper_2408_05962_amd.build``.
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -50,7 +51,35 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    write_isa_digest(bdir)
     return LIB
+
+
+ISA_DIGEST = os.path.join(HERE, "_build", "device_isa.sha256")
+
+
+def write_isa_digest(bdir: str) -> str:
+    """sha256 of the gfx950 instructions of every kernel in device.hip (directives, comments and
+    metadata left out). Host-only edits of the source leave it unchanged; any kernel change alters it.
+    Measurements recorded against one digest (profiles/traffic_*.json) apply while it is unchanged."""
+    src = os.path.join(CSRC, "device.hip")
+    asm = os.path.join(bdir, "device_isa.s")
+    cmd = [HIPCC, *FLAGS, "-x", "hip", "--cuda-device-only", "-S", src, "-o", asm]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc -S failed for {src}:\n{r.stderr}")
+    h = hashlib.sha256()
+    with open(asm) as f:
+        for line in f:
+            s = line.rstrip("\n")
+            if not s.startswith("\t") or s.startswith("\t.") or s.startswith("\t;"):
+                continue
+            h.update(s.split(";")[0].rstrip().encode() + b"\n")
+    os.remove(asm)
+    digest = h.hexdigest()
+    with open(ISA_DIGEST, "w") as f:
+        f.write(digest + "\n")
+    return digest
 
 
 if __name__ == "__main__":

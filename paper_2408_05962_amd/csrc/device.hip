@@ -1137,11 +1137,16 @@ void device_state_set_spin_limit(DeviceState* s, uint32_t polls) {
 // A table that a device-ring request still uses must not be freed or run
 // elsewhere (device request ring, end of this file).
 static bool ring_request_pending(uint64_t ring_id, uint32_t pos);
-static void ring_request_wait(uint64_t ring_id, uint32_t pos);
+static bool ring_request_wait(uint64_t ring_id, uint32_t pos);
 
 void device_state_free(DeviceState* s) {
   if (!s) return;
-  if (s->ring_id) ring_request_wait(s->ring_id, s->ring_pos);
+  // a request that is still in a ring after the bounded wait keeps its tables: they are leaked, not freed
+  // under a running kernel
+  if (s->ring_id && !ring_request_wait(s->ring_id, s->ring_pos)) {
+    delete s;
+    return;
+  }
   s->exe.free_all();
   if (s->own_ws && s->ws) (void)hipFree(s->ws);
   if (s->ev) (void)hipEventDestroy(s->ev);
@@ -2039,18 +2044,19 @@ static bool pending_in(const DeviceRing* r, uint32_t pos) {
 }
 
 // Bounded wait (30 s) for a ring request before its table is freed; an idle
-// ring is started again for it.
-static void ring_request_wait(uint64_t ring_id, uint32_t pos) {
+// ring is started again for it. False if the request is still pending.
+static bool ring_request_wait(uint64_t ring_id, uint32_t pos) {
   for (int i = 0; i < 30000; ++i) {
     {
       std::lock_guard<std::mutex> g(g_ring_mu);
       auto it = g_rings.find(ring_id);
-      if (it == g_rings.end() || !pending_in(it->second, pos)) return;
+      if (it == g_rings.end() || !pending_in(it->second, pos)) return true;
       DeviceGuard on(it->second->device);
       (void)ring_keep_alive(it->second);
     }
     std::this_thread::sleep_for(std::chrono::milliseconds(1));
   }
+  return false;
 }
 
 int ring_create(int grid, uint32_t idle_ms, uint32_t cap, DeviceRing** out) {
