@@ -568,11 +568,11 @@ __device__ __forceinline__ void copy_fp8(const DevTask* t, uint64_t e0, uint64_t
 // compiled out, which keeps the register budget (and occupancy) of the
 // int32 / float32 executor higher.
 template <int BLOCK, bool NARROW>
-__device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t tile) {
+__device__ __forceinline__ void run_tile_q(const DevTask* __restrict__ t, uint32_t q) {
   const uint32_t meta = uni32(t->meta);
   const int kind = meta & 3, op = (meta >> 2) & 3, dt = (meta >> 4) & 15, k = int(meta >> 8);
   const uint64_t te = uni64(t->tile_elems);
-  const uint64_t e0 = uint64_t(tile - uni32(t->first_tile)) * te;
+  const uint64_t e0 = uint64_t(q) * te;
   const uint64_t e1 = min(e0 + te, uni64(t->count));
   const uint64_t n = e1 - e0;
   if (kind == kCopy) {
@@ -624,6 +624,12 @@ __device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t
       default: reduce_fp8<BLOCK>(t, k, e0, n); break;
     }
   }
+}
+
+// Tile `tile` of the table (its task's tiles are consecutive from first_tile).
+template <int BLOCK, bool NARROW>
+__device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t tile) {
+  run_tile_q<BLOCK, NARROW>(t, tile - uni32(t->first_tile));
 }
 
 __device__ __forceinline__ unsigned long long dev_clock() { return wall_clock64(); }
@@ -860,11 +866,19 @@ __global__ void hiccl_stamp(unsigned long long* at) {
 
 // One launch per dependency stage: the kernel boundary orders the stages,
 // so no counters are used.
+//
+// `order` lists the stage's tiles as (task, tile within the task) pairs in
+// launch order. Workgroup b runs positions b, b + grid, ...; workgroups are
+// placed on the eight XCDs round-robin, so with a grid that is a multiple of
+// 8 every position p runs on XCD p mod 8. The host puts tiles that read the
+// same source bytes (sibling hops of a multicast) at positions 8 apart:
+// they run at the same time on one XCD, whose L2 then serves the repeats.
 template <int BLOCK, bool NARROW>
-__global__ __launch_bounds__(BLOCK) void hiccl_staged(ExecArgs a, uint32_t lo, uint32_t hi) {
+__global__ __launch_bounds__(BLOCK) void hiccl_staged(ExecArgs a, const uint2* order, uint32_t lo, uint32_t hi) {
   for (uint32_t tl = lo + blockIdx.x; tl < hi; tl += gridDim.x) {
-    const uint32_t k = __builtin_amdgcn_readfirstlane(a.tile_task[tl]);
-    run_tile<BLOCK, NARROW>(a.tasks + k, tl);
+    const uint2 o = order[tl];
+    const uint32_t k = __builtin_amdgcn_readfirstlane(o.x);
+    run_tile_q<BLOCK, NARROW>(a.tasks + k, __builtin_amdgcn_readfirstlane(o.y));
   }
 }
 
@@ -1066,6 +1080,7 @@ struct Exe {
   int device = -1;
   DevTask* d_tasks = nullptr;
   uint32_t* d_tile_task = nullptr;
+  uint2* d_order = nullptr;            // staged: per position, (task, tile within the task)
   uint32_t* d_succ = nullptr;
   uint64_t* d_extra = nullptr;
   uint32_t* d_cnt = nullptr;           // pending | done | comm_left | ctl
@@ -1108,6 +1123,7 @@ struct Exe {
       (void)hipDeviceSynchronize();
       (void)hipFree(d_tasks);
       (void)hipFree(d_tile_task);
+      (void)hipFree(d_order);
       (void)hipFree(d_succ);
       (void)hipFree(d_extra);
       (void)hipFree(d_cnt);
@@ -1176,6 +1192,39 @@ static int stage_grid(int want) { return want > 0 ? want : 2 * cu_count(); }
 // Flatten plans into one device task table. ws_base[i] is plan i's workspace.
 // merge: 0 = interleave the collectives by dependency stage; 1 = smallest
 // collective first (by executed bytes), each in stage order.
+// Reorder positions [b, e) of one stage so that tiles reading the same source bytes (sibling hops of a
+// multicast read their staging rank's buffer once each) sit 8 positions apart, i.e. on one XCD at the
+// same time: groups are dealt to the 8 residues mod 8, each to the residue with the fewest rows so far,
+// and the rows are then read out in order. Tiles with no sibling keep their relative order.
+static void xcd_group(const std::vector<DevTask>& h, std::vector<uint2>& order, uint32_t b, uint32_t e) {
+  if (e - b < 2) return;
+  std::unordered_map<uint64_t, uint32_t> gid;
+  std::vector<std::vector<uint2>> groups;
+  for (uint32_t p = b; p < e; ++p) {
+    const DevTask& d = h[order[p].x];
+    const uint32_t dt = (d.meta >> 4) & 15, k = d.meta >> 8;
+    const uint64_t es = dt == HICCL_BFLOAT16 ? 2 : (dt == HICCL_FP8_E4M3 ? 1 : 4);
+    const uint64_t key = k <= 4 ? d.src[0] + uint64_t(order[p].y) * d.tile_elems * es : ~uint64_t(order[p].x);
+    auto it = gid.find(key);
+    if (it == gid.end()) {
+      it = gid.emplace(key, uint32_t(groups.size())).first;
+      groups.emplace_back();
+    }
+    groups[it->second].push_back(order[p]);
+  }
+  if (groups.size() == e - b) return;
+  uint64_t rows[8] = {};
+  std::vector<std::pair<uint64_t, uint2>> placed;
+  placed.reserve(e - b);
+  for (const auto& g : groups) {
+    const int x = int(std::min_element(rows, rows + 8) - rows);
+    for (size_t i = 0; i < g.size(); ++i) placed.push_back({(rows[x] + i) * 8 + uint64_t(x), g[i]});
+    rows[x] += g.size();
+  }
+  std::sort(placed.begin(), placed.end(), [](const auto& u, const auto& v) { return u.first < v.first; });
+  for (uint32_t i = 0; i < e - b; ++i) order[b + i] = placed[i].second;
+}
+
 static int upload(const std::vector<const Plan*>& plans, const std::vector<uint64_t>& ws_base, int mode, int grid,
                   uint32_t spin_limit, bool with_times, Exe& ex, int queues = kMaxQueues,
                   int batch = HICCL_CLAIM_BATCH, int merge = 0) {
@@ -1261,11 +1310,20 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
   }
   for (int s = nstages - 1; s >= 0; --s) ex.stage_tile_begin[s] = std::min(ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1]);
 
+  // Launch order of stage launches: per position, (task, tile within the task). Within each stage of a
+  // stage-sorted table, tiles that read the same source bytes are grouped onto one XCD (hiccl_staged).
+  std::vector<uint2> order(tile_task.size());
+  for (size_t tl = 0; tl < tile_task.size(); ++tl)
+    order[tl] = make_uint2(tile_task[tl], uint32_t(tl - h[tile_task[tl]].first_tile));
+  if (mode == HICCL_EXEC_STAGED || (plans.size() > 1 && merge == 0))
+    for (int s = 0; s < nstages; ++s) xcd_group(h, order, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1]);
+
   auto alloc_copy = [&](void** dptr, const void* src, size_t bytes) -> int {
     HIP_TRY(hipMalloc(dptr, std::max<size_t>(bytes, 16)));
     if (bytes) HIP_TRY(hipMemcpy(*dptr, src, bytes, hipMemcpyHostToDevice));
     return 0;
   };
+  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_order), order.data(), order.size() * sizeof(uint2))) return rc;
   if (!extra.empty()) {
     if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_extra), extra.data(), extra.size() * 8)) return rc;
     for (auto& f : extra_fix) {
@@ -1300,9 +1358,9 @@ static int launch_stage(const Exe& ex, hipStream_t st, uint32_t lo, uint32_t hi)
   const uint32_t want = uint32_t(stage_grid(ex.stage_grid));
   int g = int(std::min<uint32_t>(hi - lo, want));
   if (ex.narrow)
-    hipLaunchKernelGGL((hiccl_staged<kBlock, true>), dim3(g), dim3(kBlock), 0, st, a, lo, hi);
+    hipLaunchKernelGGL((hiccl_staged<kBlock, true>), dim3(g), dim3(kBlock), 0, st, a, ex.d_order, lo, hi);
   else
-    hipLaunchKernelGGL((hiccl_staged<kBlock, false>), dim3(g), dim3(kBlock), 0, st, a, lo, hi);
+    hipLaunchKernelGGL((hiccl_staged<kBlock, false>), dim3(g), dim3(kBlock), 0, st, a, ex.d_order, lo, hi);
   HIP_TRY(hipGetLastError());
   return 0;
 }
