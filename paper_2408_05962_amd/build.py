@@ -82,5 +82,32 @@ def write_isa_digest(bdir: str) -> str:
     return digest
 
 
+def build_sanitized() -> str:
+    """A host-sanitized library for the CPU tests: AddressSanitizer and UndefinedBehaviorSanitizer on the
+    host code only (device code is built as usual). Run the CPU suite against it with
+    HICCL_LIB=<path> LD_PRELOAD="$(gcc -print-file-name=libasan.so) $(gcc -print-file-name=libubsan.so)"
+    ASAN_OPTIONS=detect_leaks=0 python -m pytest tests -m "not gpu"."""
+    bdir = os.path.join(HERE, "_build", "sanitize")
+    os.makedirs(bdir, exist_ok=True)
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer"]
+    objs = []
+    for src in sources():
+        obj = os.path.join(bdir, os.path.basename(src) + ".o")
+        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g"]
+        r = subprocess.run([HIPCC, *flags, *san, *lang, "-c", src, "-o", obj], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+        objs.append(obj)
+    out = os.path.join(bdir, "libhiccl_sanitize.so")
+    # the host linker adds the sanitizer runtimes; the device code is already embedded in the objects
+    r = subprocess.run(["g++", "-shared", "-fPIC", "-fsanitize=address,undefined", *objs, "-L/opt/rocm/lib",
+                        "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-o", out], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    return out
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build_sanitized() if "--sanitize" in sys.argv else build(verbose="-v" in sys.argv))
