@@ -57,7 +57,7 @@ enum { CTL_EXIT = kMaxQueues * kLine, CTL_ABORT = CTL_EXIT + 1, CTL_STATUS = CTL
 
 struct ExecArgs {
   const DevTask* tasks;
-  const uint32_t* tile_task;
+  const uint2* order;       // per table position: (task, tile within the task)
   const uint32_t* succ;
   uint32_t* pending;        // per task: retired predecessors this run
   uint32_t* done;           // per task: retired tiles this run
@@ -564,11 +564,12 @@ __device__ __forceinline__ void copy_fp8(const DevTask* t, uint64_t e0, uint64_t
     st4(rds, tid * 4u, v);
 }
 
-// NARROW = the table may hold bf16 / fp8 tasks; without it those paths are
-// compiled out, which keeps the register budget (and occupancy) of the
-// int32 / float32 executor higher.
+// Run tile q (counted from 0 within its task) of task t. NARROW = the table
+// may hold bf16 / fp8 tasks; without it those paths are compiled out, which
+// keeps the register budget (and occupancy) of the int32 / float32 executor
+// higher.
 template <int BLOCK, bool NARROW>
-__device__ __forceinline__ void run_tile_q(const DevTask* __restrict__ t, uint32_t q) {
+__device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t q) {
   const uint32_t meta = uni32(t->meta);
   const int kind = meta & 3, op = (meta >> 2) & 3, dt = (meta >> 4) & 15, k = int(meta >> 8);
   const uint64_t te = uni64(t->tile_elems);
@@ -624,12 +625,6 @@ __device__ __forceinline__ void run_tile_q(const DevTask* __restrict__ t, uint32
       default: reduce_fp8<BLOCK>(t, k, e0, n); break;
     }
   }
-}
-
-// Tile `tile` of the table (its task's tiles are consecutive from first_tile).
-template <int BLOCK, bool NARROW>
-__device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t tile) {
-  run_tile_q<BLOCK, NARROW>(t, tile - uni32(t->first_tile));
 }
 
 __device__ __forceinline__ unsigned long long dev_clock() { return wall_clock64(); }
@@ -753,7 +748,7 @@ __device__ __forceinline__ TileRef ref_of(const DevTask& t, uint32_t k) {
 template <int BLOCK, bool NARROW>
 __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
   __shared__ DevTask s_task[2];
-  __shared__ uint32_t s_slot[2], s_flag;
+  __shared__ uint32_t s_slot[2], s_q[2], s_flag;      // s_q: the posted tile's number within its task
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x) / 64;   // wave-uniform
   const bool sched = wave == BLOCK / 64;
   const uint32_t lane = threadIdx.x & 63u;
@@ -766,10 +761,12 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
     if (lead) tl_l = claim_next(a, c);
     uint32_t tl = __builtin_amdgcn_readfirstlane(tl_l);
     if (tl != kNoTile) {
-      const uint32_t k = __builtin_amdgcn_readfirstlane(a.tile_task[tl]);
+      const uint2 o = a.order[tl];
+      const uint32_t k = __builtin_amdgcn_readfirstlane(o.x);
       stage_desc(&s_task[0], a.tasks + k, lane);
       __builtin_amdgcn_s_waitcnt(0);   // the copy has landed before lane 0 reads it back
       if (lead) {
+        s_q[0] = o.y;
         cur_ref = ref_of(s_task[0], k);
         if (!wait_ready(a, k, s_task[0].npred)) tl = kNoTile;
       }
@@ -791,7 +788,8 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
         uint32_t nx_l = kNoTile;
         if (lead) nx_l = claim_next(a, c);
         const uint32_t nx = __builtin_amdgcn_readfirstlane(nx_l);
-        uint32_t k_l = nx != kNoTile ? a.tile_task[nx] : 0u;          // in flight during the retire below
+        const uint2 o_l = nx != kNoTile ? a.order[nx] : make_uint2(0u, 0u);   // in flight during the retire below
+        const uint32_t k_l = o_l.x;
         if (lead && have_prev) retire(a, prev_ref);
         const uint32_t knx = __builtin_amdgcn_readfirstlane(k_l);
         uint32_t post = kNoTile;
@@ -808,6 +806,7 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
         }
         if (lead) {
           s_slot[cur ^ 1] = post;
+          s_q[cur ^ 1] = o_l.y;
           prev_ref = cur_ref;
           if (nx != kNoTile) cur_ref = ref_of(*next, knx);
         }
@@ -818,11 +817,14 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
         stage_desc(next, &s_task[cur], lane);
         uint32_t post = kNoTile;
         if (lead) post = wait_ready(a, cur_ref.k, s_task[cur].npred) ? tl : kNoTile;
-        if (lead) s_slot[cur ^ 1] = post;
+        if (lead) {
+          s_slot[cur ^ 1] = post;
+          s_q[cur ^ 1] = s_q[cur];
+        }
       }
     } else if (ready) {
       const DevTask* t = &s_task[cur];
-      run_tile<BLOCK, NARROW>(t, tl);
+      run_tile<BLOCK, NARROW>(t, __builtin_amdgcn_readfirstlane(s_q[cur]));
       // a tile whose retire releases something (successors, a completion
       // stamp) has its stores complete before the barrier; any other tile's
       // stores drain while the next tile streams, and the kernel's end
@@ -874,11 +876,11 @@ __global__ void hiccl_stamp(unsigned long long* at) {
 // same source bytes (sibling hops of a multicast) at positions 8 apart:
 // they run at the same time on one XCD, whose L2 then serves the repeats.
 template <int BLOCK, bool NARROW>
-__global__ __launch_bounds__(BLOCK) void hiccl_staged(ExecArgs a, const uint2* order, uint32_t lo, uint32_t hi) {
+__global__ __launch_bounds__(BLOCK) void hiccl_staged(ExecArgs a, uint32_t lo, uint32_t hi) {
   for (uint32_t tl = lo + blockIdx.x; tl < hi; tl += gridDim.x) {
-    const uint2 o = order[tl];
+    const uint2 o = a.order[tl];
     const uint32_t k = __builtin_amdgcn_readfirstlane(o.x);
-    run_tile_q<BLOCK, NARROW>(a.tasks + k, __builtin_amdgcn_readfirstlane(o.y));
+    run_tile<BLOCK, NARROW>(a.tasks + k, __builtin_amdgcn_readfirstlane(o.y));
   }
 }
 
@@ -926,7 +928,7 @@ __global__ __launch_bounds__(BLOCK) void hiccl_ring(RingArgs r) {
   constexpr uint32_t kPieces = sizeof(ExecArgs) / 16;
   __shared__ ExecArgs s_args;
   __shared__ DevTask s_task;
-  __shared__ uint32_t s_word[2];
+  __shared__ uint32_t s_word[3];
   const uint32_t tid = threadIdx.x;
   const bool lead = tid == 0;
   if (blockIdx.x == 0) {
@@ -1016,18 +1018,22 @@ __global__ __launch_bounds__(BLOCK) void hiccl_ring(RingArgs r) {
         }
         uint32_t tl = __builtin_amdgcn_readfirstlane(tl_l);
         if (tl != kNoTile) {
-          const uint32_t k = __builtin_amdgcn_readfirstlane(a.tile_task[tl]);
+          const uint2 o = a.order[tl];
+          const uint32_t k = __builtin_amdgcn_readfirstlane(o.x);
           stage_desc(&s_task, a.tasks + k, lane);
           __builtin_amdgcn_s_waitcnt(0);
           if (lead && !wait_ready(a, k, s_task.npred)) tl = kNoTile;
-          if (lead) s_word[0] = k;
+          if (lead) {
+            s_word[0] = k;
+            s_word[2] = o.y;
+          }
         }
         if (lead) s_word[1] = tl;
       }
       __syncthreads();
       const uint32_t tl = __builtin_amdgcn_readfirstlane(s_word[1]);
       if (tl == kNoTile) break;
-      run_tile<BLOCK, true>(&s_task, tl);
+      run_tile<BLOCK, true>(&s_task, __builtin_amdgcn_readfirstlane(s_word[2]));
       wait_mem();
       __syncthreads();
       if (lead) retire(a, ref_of(s_task, s_word[0]));
@@ -1079,8 +1085,7 @@ constexpr int kGraphBranches = 4;     // parallel branches of the captured batch
 struct Exe {
   int device = -1;
   DevTask* d_tasks = nullptr;
-  uint32_t* d_tile_task = nullptr;
-  uint2* d_order = nullptr;            // staged: per position, (task, tile within the task)
+  uint2* d_order = nullptr;            // per table position: (task, tile within the task)
   uint32_t* d_succ = nullptr;
   uint64_t* d_extra = nullptr;
   uint32_t* d_cnt = nullptr;           // pending | done | comm_left | ctl
@@ -1099,7 +1104,7 @@ struct Exe {
   ExecArgs args() const {
     ExecArgs a;
     a.tasks = d_tasks;
-    a.tile_task = d_tile_task;
+    a.order = d_order;
     a.succ = d_succ;
     a.pending = d_cnt;
     a.done = d_cnt + ntasks;
@@ -1122,7 +1127,6 @@ struct Exe {
       (void)hipSetDevice(device);
       (void)hipDeviceSynchronize();
       (void)hipFree(d_tasks);
-      (void)hipFree(d_tile_task);
       (void)hipFree(d_order);
       (void)hipFree(d_succ);
       (void)hipFree(d_extra);
@@ -1310,12 +1314,18 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
   }
   for (int s = nstages - 1; s >= 0; --s) ex.stage_tile_begin[s] = std::min(ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1]);
 
-  // Launch order of stage launches: per position, (task, tile within the task). Within each stage of a
-  // stage-sorted table, tiles that read the same source bytes are grouped onto one XCD (hiccl_staged).
+  // Claim / launch order: per position, (task, tile within the task). In a stage-sorted table, tiles
+  // that read the same source bytes are grouped onto one XCD within each stage: stage launches run
+  // position p on XCD p mod 8 (hiccl_staged), and the persistent executor deals position p to queue
+  // p mod 8, served by the workgroups of XCD p mod 8 (claim_next). Any order inside a stage is
+  // topological, since a task's predecessors all lie in earlier stages.
   std::vector<uint2> order(tile_task.size());
   for (size_t tl = 0; tl < tile_task.size(); ++tl)
     order[tl] = make_uint2(tile_task[tl], uint32_t(tl - h[tile_task[tl]].first_tile));
-  if (mode == HICCL_EXEC_STAGED || (plans.size() > 1 && merge == 0))
+  bool stage_sorted = true;
+  for (size_t i = 1; i < nt && stage_sorted; ++i)
+    stage_sorted = plans[refs[i - 1].plan]->tasks[refs[i - 1].idx].stage <= plans[refs[i].plan]->tasks[refs[i].idx].stage;
+  if (stage_sorted)
     for (int s = 0; s < nstages; ++s) xcd_group(h, order, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1]);
 
   auto alloc_copy = [&](void** dptr, const void* src, size_t bytes) -> int {
@@ -1333,7 +1343,6 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
     }
   }
   if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_tasks), h.data(), h.size() * sizeof(DevTask))) return rc;
-  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_tile_task), tile_task.data(), tile_task.size() * 4)) return rc;
   if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_succ), succ.data(), succ.size() * 4)) return rc;
   if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_comm_ntasks), comm_n.data(), comm_n.size() * 4)) return rc;
   size_t ncnt = 2 * nt + plans.size() + kCtlWords;
@@ -1358,9 +1367,9 @@ static int launch_stage(const Exe& ex, hipStream_t st, uint32_t lo, uint32_t hi)
   const uint32_t want = uint32_t(stage_grid(ex.stage_grid));
   int g = int(std::min<uint32_t>(hi - lo, want));
   if (ex.narrow)
-    hipLaunchKernelGGL((hiccl_staged<kBlock, true>), dim3(g), dim3(kBlock), 0, st, a, ex.d_order, lo, hi);
+    hipLaunchKernelGGL((hiccl_staged<kBlock, true>), dim3(g), dim3(kBlock), 0, st, a, lo, hi);
   else
-    hipLaunchKernelGGL((hiccl_staged<kBlock, false>), dim3(g), dim3(kBlock), 0, st, a, ex.d_order, lo, hi);
+    hipLaunchKernelGGL((hiccl_staged<kBlock, false>), dim3(g), dim3(kBlock), 0, st, a, lo, hi);
   HIP_TRY(hipGetLastError());
   return 0;
 }
