@@ -1197,10 +1197,15 @@ static int stage_grid(int want) { return want > 0 ? want : 2 * cu_count(); }
 // merge: 0 = interleave the collectives by dependency stage; 1 = smallest
 // collective first (by executed bytes), each in stage order.
 // Reorder positions [b, e) of one stage so that tiles reading the same source bytes (sibling hops of a
-// multicast read their staging rank's buffer once each) sit 8 positions apart, i.e. on one XCD at the
-// same time: groups are dealt to the 8 residues mod 8, each to the residue with the fewest rows so far,
-// and the rows are then read out in order. Tiles with no sibling keep their relative order.
-static void xcd_group(const std::vector<DevTask>& h, std::vector<uint2>& order, uint32_t b, uint32_t e) {
+// multicast read their staging rank's buffer once each) land on one XCD at the same time. Position p
+// runs on XCD p mod 8. Groups of same-source tiles are dealt to lanes (a residue mod 8 and a row offset
+// j < spread), each to the lane holding the fewest tiles so far; the n-th tile of lane (x, j) goes to
+// row n * spread + j of residue x. With spread = 1 a group's tiles are 8 positions apart; the
+// persistent executor claims `spread` consecutive positions of a queue at once, so there a group's
+// tiles are spread * 8 apart and fall into different claims. Tiles with no sibling keep their
+// relative order.
+static void xcd_group(const std::vector<DevTask>& h, std::vector<uint2>& order, uint32_t b, uint32_t e,
+                      uint32_t spread) {
   if (e - b < 2) return;
   std::unordered_map<uint64_t, uint32_t> gid;
   std::vector<std::vector<uint2>> groups;
@@ -1217,13 +1222,15 @@ static void xcd_group(const std::vector<DevTask>& h, std::vector<uint2>& order, 
     groups[it->second].push_back(order[p]);
   }
   if (groups.size() == e - b) return;
-  uint64_t rows[8] = {};
+  const uint32_t lanes = 8 * spread;
+  std::vector<uint64_t> fill(lanes, 0);
   std::vector<std::pair<uint64_t, uint2>> placed;
   placed.reserve(e - b);
   for (const auto& g : groups) {
-    const int x = int(std::min_element(rows, rows + 8) - rows);
-    for (size_t i = 0; i < g.size(); ++i) placed.push_back({(rows[x] + i) * 8 + uint64_t(x), g[i]});
-    rows[x] += g.size();
+    const uint32_t l = uint32_t(std::min_element(fill.begin(), fill.end()) - fill.begin());
+    const uint64_t x = l % 8, j = l / 8;
+    for (size_t i = 0; i < g.size(); ++i) placed.push_back({((fill[l] + i) * spread + j) * 8 + x, g[i]});
+    fill[l] += g.size();
   }
   std::sort(placed.begin(), placed.end(), [](const auto& u, const auto& v) { return u.first < v.first; });
   for (uint32_t i = 0; i < e - b; ++i) order[b + i] = placed[i].second;
@@ -1325,8 +1332,9 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
   bool stage_sorted = true;
   for (size_t i = 1; i < nt && stage_sorted; ++i)
     stage_sorted = plans[refs[i - 1].plan]->tasks[refs[i - 1].idx].stage <= plans[refs[i].plan]->tasks[refs[i].idx].stage;
+  const uint32_t spread = mode == HICCL_EXEC_STAGED ? 1u : uint32_t(std::max(1, batch));
   if (stage_sorted)
-    for (int s = 0; s < nstages; ++s) xcd_group(h, order, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1]);
+    for (int s = 0; s < nstages; ++s) xcd_group(h, order, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1], spread);
 
   auto alloc_copy = [&](void** dptr, const void* src, size_t bytes) -> int {
     HIP_TRY(hipMalloc(dptr, std::max<size_t>(bytes, 16)));
