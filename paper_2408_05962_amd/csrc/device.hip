@@ -869,8 +869,9 @@ __global__ void hiccl_stamp(unsigned long long* at) {
 // One launch per dependency stage: the kernel boundary orders the stages,
 // so no counters are used.
 //
-// `order` lists the stage's tiles as (task, tile within the task) pairs in
-// launch order. Workgroup b runs positions b, b + grid, ...; workgroups are
+// a.order lists the table's tiles as (task, tile within the task) pairs; a
+// stage is positions [lo, hi). Workgroup b runs positions lo + b, lo + b +
+// grid, ...; workgroups are
 // placed on the eight XCDs round-robin, so with a grid that is a multiple of
 // 8 every position p runs on XCD p mod 8. The host puts tiles that read the
 // same source bytes (sibling hops of a multicast) at positions 8 apart:
