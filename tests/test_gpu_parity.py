@@ -102,11 +102,13 @@ def test_staged_matches_persistent(torch_cuda, name):
     assert np.array_equal(a[0].view(np.uint32), e[0].view(np.uint32))
 
 
+@pytest.mark.parametrize("name", ["all_reduce", "broadcast", "all_gather"])
 @pytest.mark.parametrize("mode", ["persistent", "staged"])
 @pytest.mark.parametrize("grid,claim", [(1, None), (7, (8, 1)), (300, (3, 5)), (1000, (8, 16))])
-def test_launch_shapes_do_not_change_results(torch_cuda, mode, grid, claim):
-    """Grid, queue count and claim batch decide only who runs which tile, never the arithmetic."""
-    name, h, s, m, p = "all_reduce", [2, 4, 2], 4, 2, 16
+def test_launch_shapes_do_not_change_results(torch_cuda, name, mode, grid, claim):
+    """Grid, queue count and claim batch decide only who runs which tile (and on which XCD), never the
+    arithmetic; Broadcast and All-Gather exercise the grouping of same-source tiles."""
+    h, s, m, p = [2, 4, 2], 4, 2, 16
     sends, ref = _run(torch_cuda, name, p, h, "float32", 2048 + 5, s=s, m=m, seed=21, tile=4096)
     _, got = _run(torch_cuda, name, p, h, "float32", 2048 + 5, s=s, m=m, sends=sends, tile=4096, mode=mode,
                   grid=grid, claim=claim, reps=2)

@@ -218,3 +218,57 @@ def test_serving_mix_full_size_alone_and_in_the_mix(torch_cuda):
             assert torch.equal(temps[k]["rcv"], alone[k]), (ring, k, temps[k]["name"], temps[k]["dtype"])
     for tp in temps:
         tp["comm"].close()
+
+
+@pytest.mark.parametrize("dtype", ["bfloat16", "fp8_e4m3"])
+def test_ring_payload_requests_bit_identical(torch_cuda, dtype):
+    """bf16 and fp8 requests through the device ring equal the same requests run alone, bit for bit (codes
+    and block scales)."""
+    torch = torch_cuda
+    import synth
+    from paper_2408_05962_amd import Server, to_payload
+    from paper_2408_05962_amd import collectives as CO
+    st = torch.cuda.current_stream()
+    temps = []
+    for i, (name, h) in enumerate([("all_reduce", [2, 4, 2]), ("reduce_scatter", [4, 4]), ("broadcast", [2, 4]),
+                                   ("all_gather", [2, 4, 2])]):
+        p = int(np.prod(h))
+        d = 256 * 12
+        n_s, n_r = H.send_len(name, p, d), H.recv_len(name, p, d)
+        X = synth.device_buffers("float32_outliers", 600 + i, p, n_s)
+        if dtype == "bfloat16":
+            S = torch.empty((p, n_s), dtype=torch.int16, device="cuda")
+            for r in range(p):
+                to_payload(dtype, X[r], S[r], None, n_s, st)
+            R = torch.zeros((p, n_r), dtype=torch.int16, device="cuda")
+            send, recv, scales = [S[r] for r in range(p)], [R[r] for r in range(p)], None
+            SS = None
+        else:
+            S = torch.empty((p, n_s), dtype=torch.uint8, device="cuda")
+            SS = torch.empty((p, n_s // 256), device="cuda")
+            for r in range(p):
+                to_payload(dtype, X[r], S[r], SS[r], n_s, st)
+            R = torch.zeros((p, n_r), dtype=torch.uint8, device="cuda")
+            RS = torch.zeros((p, n_r // 256), device="cuda")
+            send, recv, scales = [(S[r], SS[r]) for r in range(p)], [(R[r], RS[r]) for r in range(p)], RS
+        c = CO.make(name, p, dtype, send, recv, d, hierarchy=h, stripe=2, pipeline=2, tile_bytes=4096)
+        c.set_spin_limit(1 << 20)
+        c.run(st)
+        c.wait()
+        alone = (R.clone(), scales.clone() if scales is not None else None)
+        # the communicator holds raw addresses: every buffer it names (send scales included) must outlive it
+        temps.append({"c": c, "R": R, "scales": scales, "alone": alone, "keep": (X, S, SS)})
+    srv = Server(1 << 40, 2, ring=True, idle_ms=50)
+    for rnd in range(2):
+        for tp in temps:
+            tp["R"].zero_()
+            if tp["scales"] is not None:
+                tp["scales"].zero_()
+        _serve(torch, srv, [{"c": tp["c"]} for tp in temps], list(range(len(temps))))
+        for k, tp in enumerate(temps):
+            assert torch.equal(tp["R"], tp["alone"][0]), (dtype, rnd, k)
+            if tp["scales"] is not None:
+                assert torch.equal(tp["scales"], tp["alone"][1]), (dtype, rnd, k)
+    srv.close()
+    for tp in temps:
+        tp["c"].close()
