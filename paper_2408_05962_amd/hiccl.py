@@ -176,18 +176,24 @@ class Comm:
         h = C.c_void_p()
         check(lib().hiccl_comm_create(nranks, self.dtype, C.byref(h)))
         self.h = h
+        self._buffers = []   # the buffer objects passed in: the library keeps only their addresses
 
     # composition (Sec. 3.1) -------------------------------------------------
     def add_multicast(self, send, recv, count, root, leaves):
-        """send / recv: per-rank addresses (or (data, scales) pairs); None where unused."""
+        """send / recv: per-rank addresses (or (data, scales) pairs); None where unused. Tensors and
+        arrays passed here are kept referenced for the communicator's lifetime."""
         lv, n = _ints(leaves)
-        return check(lib().hiccl_add_multicast(self.h, _bufs(send, self.nranks), _bufs(recv, self.nranks),
-                                               int(count), int(root), lv, n))
+        check(lib().hiccl_add_multicast(self.h, _bufs(send, self.nranks), _bufs(recv, self.nranks),
+                                        int(count), int(root), lv, n))
+        self._buffers.append((send, recv))
+        return SUCCESS
 
     def add_reduction(self, send, recv, count, leaves, root, op="sum"):
         lv, n = _ints(leaves)
-        return check(lib().hiccl_add_reduction(self.h, _bufs(send, self.nranks), _bufs(recv, self.nranks),
-                                               int(count), lv, n, int(root), OPS[op] if isinstance(op, str) else op))
+        check(lib().hiccl_add_reduction(self.h, _bufs(send, self.nranks), _bufs(recv, self.nranks),
+                                        int(count), lv, n, int(root), OPS[op] if isinstance(op, str) else op))
+        self._buffers.append((send, recv))
+        return SUCCESS
 
     def add_fence(self):
         return check(lib().hiccl_add_fence(self.h))
@@ -231,7 +237,9 @@ class Comm:
         return v.value
 
     def set_workspace(self, buf, nbytes):
-        return check(lib().hiccl_set_workspace(self.h, addr(buf), int(nbytes)))
+        check(lib().hiccl_set_workspace(self.h, addr(buf), int(nbytes)))
+        self._buffers.append(buf)
+        return SUCCESS
 
     # execution ------------------------------------------------------------------
     def run(self, stream=None):
@@ -276,6 +284,7 @@ class Comm:
         if getattr(self, "h", None):
             lib().hiccl_comm_destroy(self.h)
             self.h = None
+            self._buffers = []
 
     def __del__(self):
         try:
