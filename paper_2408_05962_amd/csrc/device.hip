@@ -129,9 +129,16 @@ constexpr int kUnroll = 8;     // 16-byte vectors in flight per lane and operand
 // "stores complete" (s_waitcnt) and a counter increment, with no L2-wide
 // writeback or invalidate. The buffer range of each operand is exactly the
 // tile, so the hardware bounds check drops any access outside it.
+//
+// Stage launches store without the streaming hint (sc1 only). Their
+// consumers run in a later launch, and the end of a launch writes the
+// L2 back, so visibility holds there too. The stores then stay in the
+// caches, where the next stage finds the last of them (its tiles run in
+// the opposite order, see upload).
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 constexpr int kPolicy = 2 | 16;               // nt | sc1
+constexpr int kStagePolicy = 16;              // sc1: stores of stage launches
 constexpr int kRsrcWord3 = 0x00020000;        // raw (untyped) buffer, gfx9 family
 
 __device__ __forceinline__ rsrc_t rsrc(uint64_t base, uint64_t bytes) {
@@ -141,33 +148,37 @@ __device__ __forceinline__ uint4 ld16(rsrc_t r, uint32_t off) {
   v4u v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, kPolicy);
   return make_uint4(v.x, v.y, v.z, v.w);
 }
+template <int SP = kPolicy>
 __device__ __forceinline__ void st16(rsrc_t r, uint32_t off, uint4 x) {
   v4u v = {x.x, x.y, x.z, x.w};
-  __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, kPolicy);
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, off, 0, SP);
 }
 __device__ __forceinline__ uint32_t ld4(rsrc_t r, uint32_t off) {
   return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, kPolicy);
 }
+template <int SP = kPolicy>
 __device__ __forceinline__ void st4(rsrc_t r, uint32_t off, uint32_t x) {
-  __builtin_amdgcn_raw_buffer_store_b32(x, r, off, 0, kPolicy);
+  __builtin_amdgcn_raw_buffer_store_b32(x, r, off, 0, SP);
 }
 __device__ __forceinline__ uint32_t ld2(rsrc_t r, uint32_t off) {
   return __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, kPolicy);
 }
+template <int SP = kPolicy>
 __device__ __forceinline__ void st2(rsrc_t r, uint32_t off, uint32_t x) {
-  __builtin_amdgcn_raw_buffer_store_b16(uint16_t(x), r, off, 0, kPolicy);
+  __builtin_amdgcn_raw_buffer_store_b16(uint16_t(x), r, off, 0, SP);
 }
 __device__ __forceinline__ uint32_t ld1(rsrc_t r, uint32_t off) {
   return __builtin_amdgcn_raw_buffer_load_b8(r, off, 0, kPolicy);
 }
+template <int SP = kPolicy>
 __device__ __forceinline__ void st1(rsrc_t r, uint32_t off, uint32_t x) {
-  __builtin_amdgcn_raw_buffer_store_b8(uint8_t(x), r, off, 0, kPolicy);
+  __builtin_amdgcn_raw_buffer_store_b8(uint8_t(x), r, off, 0, SP);
 }
 // wait until this wave's loads and stores have completed
 __device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 // Copy nb bytes (one tile) from s to d.
-template <int BLOCK>
+template <int BLOCK, int SP = kPolicy>
 __device__ __forceinline__ void copy_bytes(uint64_t s, uint64_t d, uint64_t nb) {
   const uint32_t tid = threadIdx.x;
   const rsrc_t rs = rsrc(s, nb), rd = rsrc(d, nb);
@@ -179,7 +190,7 @@ __device__ __forceinline__ void copy_bytes(uint64_t s, uint64_t d, uint64_t nb) 
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) r[u] = ld16(rs, (i + u * BLOCK) * 16u);
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) st16(rd, (i + u * BLOCK) * 16u, r[u]);
+      for (int u = 0; u < kUnroll; ++u) st16<SP>(rd, (i + u * BLOCK) * 16u, r[u]);
     }
     if (i < nv) {   // the last (at most kUnroll - 1) vectors of this lane, loads still all in flight
       uint4 r[kUnroll];
@@ -188,15 +199,15 @@ __device__ __forceinline__ void copy_bytes(uint64_t s, uint64_t d, uint64_t nb) 
         if (i + u * BLOCK < nv) r[u] = ld16(rs, (i + u * BLOCK) * 16u);
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u)
-        if (i + u * BLOCK < nv) st16(rd, (i + u * BLOCK) * 16u, r[u]);
+        if (i + u * BLOCK < nv) st16<SP>(rd, (i + u * BLOCK) * 16u, r[u]);
     }
-    for (uint32_t b = (nv << 4) + tid; b < nb; b += BLOCK) st1(rd, b, ld1(rs, b));
+    for (uint32_t b = (nv << 4) + tid; b < nb; b += BLOCK) st1<SP>(rd, b, ld1(rs, b));
   } else if (((s | d) & 3u) == 0) {
     const uint32_t nw = uint32_t(nb >> 2);
-    for (uint32_t i = tid; i < nw; i += BLOCK) st4(rd, i * 4u, ld4(rs, i * 4u));
-    for (uint32_t b = (nw << 2) + tid; b < nb; b += BLOCK) st1(rd, b, ld1(rs, b));
+    for (uint32_t i = tid; i < nw; i += BLOCK) st4<SP>(rd, i * 4u, ld4(rs, i * 4u));
+    for (uint32_t b = (nw << 2) + tid; b < nb; b += BLOCK) st1<SP>(rd, b, ld1(rs, b));
   } else {
-    for (uint32_t b = tid; b < nb; b += BLOCK) st1(rd, b, ld1(rs, b));
+    for (uint32_t b = tid; b < nb; b += BLOCK) st1<SP>(rd, b, ld1(rs, b));
   }
 }
 
@@ -237,7 +248,7 @@ __device__ __forceinline__ uint4 op32v(uint4 a, uint4 b) {
 // elements starting at element e0. Operands are combined left to right:
 // ((s0 op s1) op s2) ... in float32 / int32, so the result depends only on
 // the schedule, never on timing.
-template <int BLOCK, bool FLT, int OP, int K>
+template <int BLOCK, bool FLT, int OP, int K, int SP = kPolicy>
 __device__ __forceinline__ void reduce32(const DevTask* t, int k, uint64_t e0, uint64_t n) {
   const uint32_t tid = threadIdx.x;
   const int kk = K ? K : k;
@@ -264,7 +275,7 @@ __device__ __forceinline__ void reduce32(const DevTask* t, int k, uint64_t e0, u
           uint4 acc = v[0][u];
 #pragma unroll
           for (int j = 1; j < (K ? K : 1); ++j) acc = op32v<FLT, OP>(acc, v[j][u]);
-          st16(rd, (i + u * BLOCK) * 16u, acc);
+          st16<SP>(rd, (i + u * BLOCK) * 16u, acc);
         }
       }
       if (i < nv) {   // predicated last pass: every remaining load of this lane in flight together
@@ -280,7 +291,7 @@ __device__ __forceinline__ void reduce32(const DevTask* t, int k, uint64_t e0, u
             uint4 acc = v[0][u];
 #pragma unroll
             for (int j = 1; j < (K ? K : 1); ++j) acc = op32v<FLT, OP>(acc, v[j][u]);
-            st16(rd, (i + u * BLOCK) * 16u, acc);
+            st16<SP>(rd, (i + u * BLOCK) * 16u, acc);
           }
         }
         i = nv;
@@ -300,24 +311,24 @@ __device__ __forceinline__ void reduce32(const DevTask* t, int k, uint64_t e0, u
           for (int u = 0; u < kUnroll; ++u) acc[u] = op32v<FLT, OP>(acc[u], v[u]);
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) st16(rd, (i + u * BLOCK) * 16u, acc[u]);
+        for (int u = 0; u < kUnroll; ++u) st16<SP>(rd, (i + u * BLOCK) * 16u, acc[u]);
       }
     }
     for (; i < nv; i += BLOCK) {
       uint4 acc = ld16(rsrc(src_addr(t, 0, kk) + e0 * 4, nb), i * 16u);
       for (int j = 1; j < kk; ++j) acc = op32v<FLT, OP>(acc, ld16(rsrc(src_addr(t, j, kk) + e0 * 4, nb), i * 16u));
-      st16(rd, i * 16u, acc);
+      st16<SP>(rd, i * 16u, acc);
     }
   }
   for (uint32_t e = (nv << 2) + tid; e < n; e += BLOCK) {
     uint32_t acc = ld4(rsrc(src_addr(t, 0, kk) + e0 * 4, nb), e * 4u);
     for (int j = 1; j < kk; ++j) acc = op32<FLT, OP>(acc, ld4(rsrc(src_addr(t, j, kk) + e0 * 4, nb), e * 4u));
-    st4(rd, e * 4u, acc);
+    st4<SP>(rd, e * 4u, acc);
   }
 }
 
 // bf16 payload: widen to float32, sum left to right, narrow (RNE).
-template <int BLOCK>
+template <int BLOCK, int SP = kPolicy>
 __device__ __forceinline__ void reduce_bf16(const DevTask* t, int k, uint64_t e0, uint64_t n) {
   const uint32_t tid = threadIdx.x;
   const uint64_t nb = n * 2;
@@ -334,7 +345,7 @@ __device__ __forceinline__ void reduce_bf16(const DevTask* t, int k, uint64_t e0
 #pragma unroll
       for (int q = 0; q < 8; ++q) a[q] = j == 0 ? v[q] : a[q] + v[q];
     }
-    st16(rd, i * 16u,
+    st16<SP>(rd, i * 16u,
          make_uint4(pack_bf16(a[0], a[1]), pack_bf16(a[2], a[3]), pack_bf16(a[4], a[5]), pack_bf16(a[6], a[7])));
   }
   for (uint32_t e = (nv << 3) + tid; e < n; e += BLOCK) {
@@ -343,7 +354,7 @@ __device__ __forceinline__ void reduce_bf16(const DevTask* t, int k, uint64_t e0
       float v = __uint_as_float(ld2(rsrc(src_addr(t, j, k) + e0 * 2, nb), e * 2u) << 16);
       a = j == 0 ? v : a + v;
     }
-    st2(rd, e * 2u, to_bf16(a));
+    st2<SP>(rd, e * 2u, to_bf16(a));
   }
 }
 
@@ -352,7 +363,7 @@ __device__ __forceinline__ void reduce_bf16(const DevTask* t, int k, uint64_t e0
 // cross-lane exchanges, pick the new scale, and lane 0 of the group stores
 // it. Counts and offsets are whole blocks, so a group is never split, and
 // every lane runs the same number of iterations.
-template <int BLOCK>
+template <int BLOCK, int SP = kPolicy>
 __device__ __forceinline__ void reduce_fp8(const DevTask* t, int k, uint64_t e0, uint64_t n) {
   const uint32_t tid = threadIdx.x;
   const rsrc_t rd = rsrc(uni64(t->dst) + e0, n);
@@ -386,8 +397,8 @@ __device__ __forceinline__ void reduce_fp8(const DevTask* t, int k, uint64_t e0,
       uint32_t o[4] = {0, 0, 0, 0};
 #pragma unroll
       for (int q = 0; q < 16; ++q) o[q >> 2] |= enc_e4m3(ldexpf(a[q], -e)) << ((q & 3) * 8);
-      st16(rd, i * 16u, make_uint4(o[0], o[1], o[2], o[3]));
-      if ((i & 15u) == 0) st4(rdsc, (i >> 4) * 4u, __float_as_uint(amax == 0.f ? 1.f : ldexpf(1.f, e)));
+      st16<SP>(rd, i * 16u, make_uint4(o[0], o[1], o[2], o[3]));
+      if ((i & 15u) == 0) st4<SP>(rdsc, (i >> 4) * 4u, __float_as_uint(amax == 0.f ? 1.f : ldexpf(1.f, e)));
     }
   }
 }
@@ -396,7 +407,7 @@ __device__ __forceinline__ void reduce_fp8(const DevTask* t, int k, uint64_t e0,
 // operand's 16-byte load of U vectors is in flight before the first add, so
 // a lane keeps K*U loads outstanding instead of one. Same left-to-right
 // float32 order and RNE narrowing as reduce_bf16.
-template <int BLOCK, int K>
+template <int BLOCK, int K, int SP = kPolicy>
 __device__ __forceinline__ void reduce_bf16_k(const DevTask* t, uint64_t e0, uint64_t n) {
   constexpr int U = K >= 4 ? 4 : 8;             // 16-byte vectors per lane and operand in flight
   const uint32_t tid = threadIdx.x;
@@ -430,7 +441,7 @@ __device__ __forceinline__ void reduce_bf16_k(const DevTask* t, uint64_t e0, uin
         a[4] += bf16lo(w[j][u].z); a[5] += bf16hi(w[j][u].z);
         a[6] += bf16lo(w[j][u].w); a[7] += bf16hi(w[j][u].w);
       }
-      st16(rd, (i + u * BLOCK) * 16u,
+      st16<SP>(rd, (i + u * BLOCK) * 16u,
            make_uint4(pack_bf16(a[0], a[1]), pack_bf16(a[2], a[3]), pack_bf16(a[4], a[5]), pack_bf16(a[6], a[7])));
     }
   }
@@ -447,7 +458,7 @@ __device__ __forceinline__ void reduce_bf16_k(const DevTask* t, uint64_t e0, uin
       a[4] += bf16lo(w[j].z); a[5] += bf16hi(w[j].z);
       a[6] += bf16lo(w[j].w); a[7] += bf16hi(w[j].w);
     }
-    st16(rd, i * 16u, make_uint4(pack_bf16(a[0], a[1]), pack_bf16(a[2], a[3]), pack_bf16(a[4], a[5]), pack_bf16(a[6], a[7])));
+    st16<SP>(rd, i * 16u, make_uint4(pack_bf16(a[0], a[1]), pack_bf16(a[2], a[3]), pack_bf16(a[4], a[5]), pack_bf16(a[6], a[7])));
   }
   for (uint32_t e = (nv << 3) + tid; e < n; e += BLOCK) {
     float a = 0.f;
@@ -456,7 +467,7 @@ __device__ __forceinline__ void reduce_bf16_k(const DevTask* t, uint64_t e0, uin
       const float v = __uint_as_float(ld2(rs[j], e * 2u) << 16);
       a = j == 0 ? v : a + v;
     }
-    st2(rd, e * 2u, to_bf16(a));
+    st2<SP>(rd, e * 2u, to_bf16(a));
   }
 }
 
@@ -472,7 +483,7 @@ __device__ __forceinline__ void reduce_bf16_k(const DevTask* t, uint64_t e0, uin
 // and encoding rounds to nearest even; after rescaling every value lies
 // within +-448, so saturation never applies. The GPU parity tests check the
 // results bit for bit against the oracle's software codec.
-template <int BLOCK, int K>
+template <int BLOCK, int K, int SP = kPolicy>
 __device__ __forceinline__ void reduce_fp8_k(const DevTask* t, uint64_t e0, uint64_t n) {
   constexpr int U = 8;                           // vectors per lane in flight (measured best)
   constexpr uint32_t kWave = U * 64;             // vectors per wave and pass: 32 blocks
@@ -534,21 +545,21 @@ __device__ __forceinline__ void reduce_fp8_k(const DevTask* t, uint64_t e0, uint
           x = __builtin_amdgcn_cvt_pk_fp8_f32(ldexpf(a[wd * 4 + 2], -e), ldexpf(a[wd * 4 + 3], -e), x, true);
           o[wd] = uint32_t(x);
         }
-        st16(rd, iv * 16u, make_uint4(o[0], o[1], o[2], o[3]));
+        st16<SP>(rd, iv * 16u, make_uint4(o[0], o[1], o[2], o[3]));
       }
       // block blk0 + L (L = 4u + r) was rescaled by row r of this step: lane L takes it
       const uint32_t sv = __float_as_uint(amax == 0.f ? 1.f : ldexpf(1.f, e));
       const uint32_t g = uint32_t(__builtin_amdgcn_ds_bpermute(int((lane & 3u) * 16u) * 4, int(sv)));
       if ((lane >> 2) == u) nsc = g;
     }
-    if (own) st4(rdsc, (blk0 + lane) * 4u, nsc);
+    if (own) st4<SP>(rdsc, (blk0 + lane) * 4u, nsc);
   }
 }
 
 // fp8 copy: codes and block scales. The scales' loads (one dword per lane)
 // go out before the codes' copy, so they complete under it instead of
 // adding a dependent round trip after it.
-template <int BLOCK>
+template <int BLOCK, int SP = kPolicy>
 __device__ __forceinline__ void copy_fp8(const DevTask* t, uint64_t e0, uint64_t n) {
   const uint32_t tid = threadIdx.x;
   const uint64_t ssc = uni64(t->src_sc[0]) + (e0 / 256) * 4, dsc = uni64(t->dst_sc) + (e0 / 256) * 4;
@@ -557,18 +568,18 @@ __device__ __forceinline__ void copy_fp8(const DevTask* t, uint64_t e0, uint64_t
   const rsrc_t rss = rsrc(ssc, uint64_t(nsw) * 4), rds = rsrc(dsc, uint64_t(nsw) * 4);
   uint32_t v = 0;
   if (one && tid < nsw) v = ld4(rss, tid * 4u);
-  copy_bytes<BLOCK>(uni64(t->src[0]) + e0, uni64(t->dst) + e0, n);
+  copy_bytes<BLOCK, SP>(uni64(t->src[0]) + e0, uni64(t->dst) + e0, n);
   if (!one)
-    copy_bytes<BLOCK>(ssc, dsc, uint64_t(nsw) * 4);
+    copy_bytes<BLOCK, SP>(ssc, dsc, uint64_t(nsw) * 4);
   else if (tid < nsw)
-    st4(rds, tid * 4u, v);
+    st4<SP>(rds, tid * 4u, v);
 }
 
 // Run tile q (counted from 0 within its task) of task t. NARROW = the table
 // may hold bf16 / fp8 tasks; without it those paths are compiled out, which
 // keeps the register budget (and occupancy) of the int32 / float32 executor
 // higher.
-template <int BLOCK, bool NARROW>
+template <int BLOCK, bool NARROW, int SP = kPolicy>
 __device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t q) {
   const uint32_t meta = uni32(t->meta);
   const int kind = meta & 3, op = (meta >> 2) & 3, dt = (meta >> 4) & 15, k = int(meta >> 8);
@@ -579,50 +590,50 @@ __device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t
   if (kind == kCopy) {
     const uint64_t es = dt == HICCL_BFLOAT16 ? 2 : (dt == HICCL_FP8_E4M3 ? 1 : 4);
     if (NARROW && dt == HICCL_FP8_E4M3) {
-      copy_fp8<BLOCK>(t, e0, n);
+      copy_fp8<BLOCK, SP>(t, e0, n);
       return;
     }
-    copy_bytes<BLOCK>(uni64(t->src[0]) + e0 * es, uni64(t->dst) + e0 * es, n * es);
+    copy_bytes<BLOCK, SP>(uni64(t->src[0]) + e0 * es, uni64(t->dst) + e0 * es, n * es);
     return;
   }
   if (dt == HICCL_FLOAT32) {
     if (op == HICCL_SUM) {
       switch (k) {
-        case 2: reduce32<BLOCK, true, HICCL_SUM, 2>(t, k, e0, n); break;
-        case 3: reduce32<BLOCK, true, HICCL_SUM, 3>(t, k, e0, n); break;
-        case 4: reduce32<BLOCK, true, HICCL_SUM, 4>(t, k, e0, n); break;
-        default: reduce32<BLOCK, true, HICCL_SUM, 0>(t, k, e0, n); break;
+        case 2: reduce32<BLOCK, true, HICCL_SUM, 2, SP>(t, k, e0, n); break;
+        case 3: reduce32<BLOCK, true, HICCL_SUM, 3, SP>(t, k, e0, n); break;
+        case 4: reduce32<BLOCK, true, HICCL_SUM, 4, SP>(t, k, e0, n); break;
+        default: reduce32<BLOCK, true, HICCL_SUM, 0, SP>(t, k, e0, n); break;
       }
     } else if (op == HICCL_MAX) {
-      reduce32<BLOCK, true, HICCL_MAX, 0>(t, k, e0, n);
+      reduce32<BLOCK, true, HICCL_MAX, 0, SP>(t, k, e0, n);
     } else {
-      reduce32<BLOCK, true, HICCL_MIN, 0>(t, k, e0, n);
+      reduce32<BLOCK, true, HICCL_MIN, 0, SP>(t, k, e0, n);
     }
   } else if (dt == HICCL_INT32) {
     if (op == HICCL_SUM) {
       switch (k) {
-        case 2: reduce32<BLOCK, false, HICCL_SUM, 2>(t, k, e0, n); break;
-        case 4: reduce32<BLOCK, false, HICCL_SUM, 4>(t, k, e0, n); break;
-        default: reduce32<BLOCK, false, HICCL_SUM, 0>(t, k, e0, n); break;
+        case 2: reduce32<BLOCK, false, HICCL_SUM, 2, SP>(t, k, e0, n); break;
+        case 4: reduce32<BLOCK, false, HICCL_SUM, 4, SP>(t, k, e0, n); break;
+        default: reduce32<BLOCK, false, HICCL_SUM, 0, SP>(t, k, e0, n); break;
       }
     } else if (op == HICCL_MAX) {
-      reduce32<BLOCK, false, HICCL_MAX, 0>(t, k, e0, n);
+      reduce32<BLOCK, false, HICCL_MAX, 0, SP>(t, k, e0, n);
     } else {
-      reduce32<BLOCK, false, HICCL_MIN, 0>(t, k, e0, n);
+      reduce32<BLOCK, false, HICCL_MIN, 0, SP>(t, k, e0, n);
     }
   } else if (NARROW && dt == HICCL_BFLOAT16) {
     switch (k) {
-      case 2: reduce_bf16_k<BLOCK, 2>(t, e0, n); break;
-      case 3: reduce_bf16_k<BLOCK, 3>(t, e0, n); break;
-      case 4: reduce_bf16_k<BLOCK, 4>(t, e0, n); break;
-      default: reduce_bf16<BLOCK>(t, k, e0, n); break;
+      case 2: reduce_bf16_k<BLOCK, 2, SP>(t, e0, n); break;
+      case 3: reduce_bf16_k<BLOCK, 3, SP>(t, e0, n); break;
+      case 4: reduce_bf16_k<BLOCK, 4, SP>(t, e0, n); break;
+      default: reduce_bf16<BLOCK, SP>(t, k, e0, n); break;
     }
   } else if (NARROW) {
     switch (k) {
-      case 2: reduce_fp8_k<BLOCK, 2>(t, e0, n); break;
-      case 3: reduce_fp8_k<BLOCK, 3>(t, e0, n); break;
-      case 4: reduce_fp8_k<BLOCK, 4>(t, e0, n); break;
-      default: reduce_fp8<BLOCK>(t, k, e0, n); break;
+      case 2: reduce_fp8_k<BLOCK, 2, SP>(t, e0, n); break;
+      case 3: reduce_fp8_k<BLOCK, 3, SP>(t, e0, n); break;
+      case 4: reduce_fp8_k<BLOCK, 4, SP>(t, e0, n); break;
+      default: reduce_fp8<BLOCK, SP>(t, k, e0, n); break;
     }
   }
 }
@@ -881,7 +892,7 @@ __global__ __launch_bounds__(BLOCK) void hiccl_staged(ExecArgs a, uint32_t lo, u
   for (uint32_t tl = lo + blockIdx.x; tl < hi; tl += gridDim.x) {
     const uint2 o = a.order[tl];
     const uint32_t k = __builtin_amdgcn_readfirstlane(o.x);
-    run_tile<BLOCK, NARROW>(a.tasks + k, __builtin_amdgcn_readfirstlane(o.y));
+    run_tile<BLOCK, NARROW, kStagePolicy>(a.tasks + k, __builtin_amdgcn_readfirstlane(o.y));
   }
 }
 
@@ -1334,6 +1345,11 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
   for (size_t i = 1; i < nt && stage_sorted; ++i)
     stage_sorted = plans[refs[i - 1].plan]->tasks[refs[i - 1].idx].stage <= plans[refs[i].plan]->tasks[refs[i].idx].stage;
   const uint32_t spread = mode == HICCL_EXEC_STAGED ? 1u : uint32_t(std::max(1, batch));
+  // Stage launches run every other stage's tiles in reverse: a stage's last tiles wrote the lines that
+  // are still in the caches, and the next stage's first tiles read them. (Any order within a stage is valid.)
+  if (stage_sorted && mode == HICCL_EXEC_STAGED)
+    for (int s = 1; s < nstages; s += 2)
+      std::reverse(order.begin() + ex.stage_tile_begin[s], order.begin() + ex.stage_tile_begin[s + 1]);
   if (stage_sorted)
     for (int s = 0; s < nstages; ++s) xcd_group(h, order, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1], spread);
 

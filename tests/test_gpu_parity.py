@@ -171,8 +171,10 @@ def test_many_reruns_stress(torch_cuda):
 
 
 @pytest.mark.parametrize("name", H.SIX)
-def test_six_collectives_16_ranks_64MiB_full_size(torch_cuda, name):
-    """Six collectives, 16 ranks as {2,4,2}, 64 MiB float32 per rank ~ N(0,1), stripe 4, pipeline 8 (bench launch)."""
+@pytest.mark.parametrize("mode", ["staged", "persistent"])
+def test_six_collectives_16_ranks_64MiB_full_size(torch_cuda, name, mode):
+    """Six collectives, 16 ranks as {2,4,2}, 64 MiB float32 per rank ~ N(0,1), stripe 4, pipeline 8, default tile
+    and grid: the bench's launch configuration (staged) and its other executor (persistent)."""
     import torch
     import synth
     from paper_2408_05962_amd import collectives as CO
@@ -183,7 +185,7 @@ def test_six_collectives_16_ranks_64MiB_full_size(torch_cuda, name):
     Sd = synth.device_buffers("float32", 2000 + H.SIX.index(name), p, sl)
     R = torch.full((p, rl), float("nan"), device="cuda")
     c = CO.make(name, p, "float32", [Sd[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=h, stripe=s,
-                pipeline=m)
+                pipeline=m, exec_mode=mode)
     sends = [x for x in Sd.cpu().numpy()]
     c.run(torch.cuda.current_stream())
     c.wait()
