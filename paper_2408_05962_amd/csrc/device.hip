@@ -1107,7 +1107,8 @@ struct Exe {
   std::vector<uint32_t> stage_tile_begin;
   int mode = HICCL_EXEC_PERSISTENT;
   int grid = 0;                    // persistent: workgroups of the launch
-  int stage_grid = 0;              // staged: workgroups per stage launch (0 = twice the resident count)
+  int stage_grid = 0;              // staged: workgroups per stage launch (0 = by stage, see launch_stage)
+  std::vector<uint8_t> stage_shared;   // per stage: some of its tiles read the same source bytes
   uint32_t spin_limit = 1u << 22;
   uint32_t queues = kMaxQueues;
   uint32_t batch = HICCL_CLAIM_BATCH;
@@ -1216,9 +1217,9 @@ static int stage_grid(int want) { return want > 0 ? want : 2 * cu_count(); }
 // persistent executor claims `spread` consecutive positions of a queue at once, so there a group's
 // tiles are spread * 8 apart and fall into different claims. Tiles with no sibling keep their
 // relative order.
-static void xcd_group(const std::vector<DevTask>& h, std::vector<uint2>& order, uint32_t b, uint32_t e,
+static bool xcd_group(const std::vector<DevTask>& h, std::vector<uint2>& order, uint32_t b, uint32_t e,
                       uint32_t spread) {
-  if (e - b < 2) return;
+  if (e - b < 2) return false;
   std::unordered_map<uint64_t, uint32_t> gid;
   std::vector<std::vector<uint2>> groups;
   for (uint32_t p = b; p < e; ++p) {
@@ -1233,7 +1234,7 @@ static void xcd_group(const std::vector<DevTask>& h, std::vector<uint2>& order, 
     }
     groups[it->second].push_back(order[p]);
   }
-  if (groups.size() == e - b) return;
+  if (groups.size() == e - b) return false;
   const uint32_t lanes = 8 * spread;
   std::vector<uint64_t> fill(lanes, 0);
   std::vector<std::pair<uint64_t, uint2>> placed;
@@ -1246,6 +1247,7 @@ static void xcd_group(const std::vector<DevTask>& h, std::vector<uint2>& order, 
   }
   std::sort(placed.begin(), placed.end(), [](const auto& u, const auto& v) { return u.first < v.first; });
   for (uint32_t i = 0; i < e - b; ++i) order[b + i] = placed[i].second;
+  return true;
 }
 
 static int upload(const std::vector<const Plan*>& plans, const std::vector<uint64_t>& ws_base, int mode, int grid,
@@ -1350,8 +1352,10 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
   if (stage_sorted && mode == HICCL_EXEC_STAGED)
     for (int s = 1; s < nstages; s += 2)
       std::reverse(order.begin() + ex.stage_tile_begin[s], order.begin() + ex.stage_tile_begin[s + 1]);
+  ex.stage_shared.assign(size_t(nstages), 1);
   if (stage_sorted)
-    for (int s = 0; s < nstages; ++s) xcd_group(h, order, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1], spread);
+    for (int s = 0; s < nstages; ++s)
+      ex.stage_shared[s] = xcd_group(h, order, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1], spread) ? 1 : 0;
 
   auto alloc_copy = [&](void** dptr, const void* src, size_t bytes) -> int {
     HIP_TRY(hipMalloc(dptr, std::max<size_t>(bytes, 16)));
@@ -1385,11 +1389,16 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
   return 0;
 }
 
-// One stage launch over tiles [lo, hi) of a staged table.
-static int launch_stage(const Exe& ex, hipStream_t st, uint32_t lo, uint32_t hi) {
+// One stage launch over tiles [lo, hi) of a staged table (stage s). By
+// default a stage whose tiles share sources (sibling hops of a multicast)
+// runs two workgroups per CU, so that a group's tiles meet on their XCD at
+// the same time; a stage of independent streams (reduce nodes, point-to-
+// point hops) runs one per CU, which streams them faster.
+static int launch_stage(const Exe& ex, hipStream_t st, size_t s, uint32_t lo, uint32_t hi) {
   if (hi <= lo) return 0;
   ExecArgs a = ex.args();
-  const uint32_t want = uint32_t(stage_grid(ex.stage_grid));
+  const bool shared = s >= ex.stage_shared.size() || ex.stage_shared[s];
+  const uint32_t want = uint32_t(ex.stage_grid > 0 ? ex.stage_grid : (shared ? stage_grid(0) : cu_count()));
   int g = int(std::min<uint32_t>(hi - lo, want));
   if (ex.narrow)
     hipLaunchKernelGGL((hiccl_staged<kBlock, true>), dim3(g), dim3(kBlock), 0, st, a, lo, hi);
@@ -1412,7 +1421,7 @@ static int launch(const Exe& ex, hipStream_t st) {
     const bool stamp = ex.d_times && ex.ncomm == 1;
     if (stamp) hipLaunchKernelGGL(hiccl_stamp, dim3(1), dim3(64), 0, st, ex.d_times + 1);
     for (size_t s = 0; s + 1 < ex.stage_tile_begin.size(); ++s)
-      if (int rc = launch_stage(ex, st, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1])) return rc;
+      if (int rc = launch_stage(ex, st, s, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1])) return rc;
     if (stamp) hipLaunchKernelGGL(hiccl_stamp, dim3(1), dim3(64), 0, st, ex.d_times);
   }
   HIP_TRY(hipGetLastError());
@@ -1628,7 +1637,7 @@ int hiccl_batch_run(hiccl_batch_t b, void* stream) {
     const Exe& ex = b->merged;
     HIP_TRY(hipEventRecord(b->stage_ev[0], st));
     for (size_t s = 0; s + 1 < ex.stage_tile_begin.size(); ++s) {
-      if (int rc = launch_stage(ex, st, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1])) return rc;
+      if (int rc = launch_stage(ex, st, s, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1])) return rc;
       HIP_TRY(hipEventRecord(b->stage_ev[s + 1], st));
     }
   } else if (b->mode == HICCL_BATCH_SERIAL) {
