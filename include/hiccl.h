@@ -172,8 +172,9 @@ int hiccl_set_share(hiccl_comm_t comm, int rank);
  * rounded to whole 16-byte vectors and whole fp8 scale blocks; hiccl_init
  * returns INVALID_ARG if a plan would need 2^31 tiles or more), grid (workgroups of the
  * persistent launch, or of each stage launch; 0 = default: one per compute
- * unit persistent; staged, two per compute unit for a stage whose tiles share
- * sources and one per compute unit for the others), claim order (hiccl_order). */
+ * unit persistent; staged, one per compute unit for an int32 / float32 stage
+ * whose tiles share no source, two per compute unit otherwise), claim order
+ * (hiccl_order). */
 int hiccl_set_exec(hiccl_comm_t comm, int mode, size_t tile_bytes, int grid, int order);
 
 /* ------------------------------------------------------------------ init */

@@ -1392,13 +1392,15 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
 // One stage launch over tiles [lo, hi) of a staged table (stage s). By
 // default a stage whose tiles share sources (sibling hops of a multicast)
 // runs two workgroups per CU, so that a group's tiles meet on their XCD at
-// the same time; a stage of independent streams (reduce nodes, point-to-
-// point hops) runs one per CU, which streams them faster.
+// the same time; a stage of independent int32 / float32 streams (reduce
+// nodes, point-to-point hops) runs one per CU, which streams them faster.
+// bf16 / fp8 tables keep two per CU: their reduce tiles spend more time in
+// arithmetic and need the second workgroup to cover memory latency.
 static int launch_stage(const Exe& ex, hipStream_t st, size_t s, uint32_t lo, uint32_t hi) {
   if (hi <= lo) return 0;
   ExecArgs a = ex.args();
-  const bool shared = s >= ex.stage_shared.size() || ex.stage_shared[s];
-  const uint32_t want = uint32_t(ex.stage_grid > 0 ? ex.stage_grid : (shared ? stage_grid(0) : cu_count()));
+  const bool two = ex.narrow || s >= ex.stage_shared.size() || ex.stage_shared[s];
+  const uint32_t want = uint32_t(ex.stage_grid > 0 ? ex.stage_grid : (two ? stage_grid(0) : cu_count()));
   int g = int(std::min<uint32_t>(hi - lo, want));
   if (ex.narrow)
     hipLaunchKernelGGL((hiccl_staged<kBlock, true>), dim3(g), dim3(kBlock), 0, st, a, lo, hi);
