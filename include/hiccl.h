@@ -93,9 +93,12 @@ typedef enum {
 /* ---------------------------------------------------------------- lifecycle */
 
 /* Create a communicator over `nranks` virtual ranks carrying `dtype`
- * elements. Defaults: hierarchy {nranks} (direct), stripe 1, ring 1,
- * pipeline 1 (Listing 2 defaults). Errors: INVALID_ARG for nranks < 1 or an
- * unknown dtype. */
+ * elements: the Comm<T> object of Listings 1 and 2, whose element type is
+ * the template argument there (Sec. 3.2 builds every collective on one
+ * such object). Defaults: hierarchy {nranks} (direct, Sec. 6.3's
+ * non-hierarchical baseline), stripe 1, ring 1, pipeline 1, as the
+ * optimization parameters of Sec. 4.1 before they are set. Errors:
+ * INVALID_ARG for nranks < 1 or an unknown dtype; OOM. */
 int hiccl_comm_create(int nranks, int dtype, hiccl_comm_t* out);
 
 /* Free the communicator, its schedule, its device tables and its own
@@ -187,11 +190,21 @@ int hiccl_set_exec(hiccl_comm_t comm, int mode, size_t tile_bytes, int grid, int
  * STATE (already initialized). */
 int hiccl_init(hiccl_comm_t comm);
 
-/* Bytes of device workspace the plan needs (partial sums and staged stripes). */
+/* Bytes of device workspace the plan needs: the intermediate buffers of
+ * the factorized schedule, i.e. the partial sums of reduction nodes held
+ * by staging ranks (Sec. 4.2) and the stripes a striped multicast stages
+ * on its owners (Sec. 4.3). The paper allocates these inside its
+ * persistent communicator at initialization (Sec. 5.2); here the caller
+ * may supply them. Errors: STATE before hiccl_init; INVALID_ARG for NULL. */
 int hiccl_workspace_size(hiccl_comm_t comm, size_t* bytes);
 
 /* Use caller-owned device memory (>= hiccl_workspace_size bytes, 256-byte
- * aligned) as the workspace instead of a library allocation. */
+ * aligned) as that workspace instead of a library allocation (Sec. 5.2's
+ * buffers, owned by the caller). The memory must stay valid while the
+ * communicator exists and must not be used by anything else while a run is
+ * in flight. Frees uploaded device tables (they are rebuilt on the next
+ * run). Errors: STATE before hiccl_init; INVALID_ARG if too small or
+ * misaligned. */
 int hiccl_set_workspace(hiccl_comm_t comm, void* dptr, size_t bytes);
 
 /* --------------------------------------------------------------- execution */
@@ -225,8 +238,14 @@ int hiccl_set_spin_limit(hiccl_comm_t comm, uint32_t polls);
 
 /* ------------------------------------------------------------- accounting */
 
-/* Logical bytes per level of ANY accounting hierarchy `acct` (product =
- * nranks), for the initialized plan: level_bytes[0] = local copies,
+/* Communication volume of the plan, per hierarchy level: the per-level
+ * form of the communication matrix of Sec. 4.5 (bytes between every pair
+ * of ranks, summed by the level at which the pair first differs). Its
+ * top-level entry is the inter-node volume behind the throughput bounds of
+ * Table 3, which the tree factorization keeps at the minimum the collective
+ * needs (Sec. 4.2). Logical bytes per
+ * level of ANY accounting hierarchy `acct` (product = nranks; NULL / 0 =
+ * the communicator's own), for the initialized plan: level_bytes[0] = local copies,
  * level_bytes[k] = transfers whose endpoints first differ at depth k
  * (1 = highest). A reduction node counts one transfer per operand held by
  * another rank. hbm_read / hbm_written = bytes the executor reads and
@@ -288,9 +307,17 @@ typedef enum {
 } hiccl_batch_mode;
 
 /* Group initialized communicators (any mix of dtypes and hierarchies) into
- * one batch. The communicators must outlive the batch and must not run on
- * their own while it exists. */
+ * one batch. Members run with no ordering between them, so they must be
+ * disjoint: no communicator twice, and no member may write caller memory
+ * (or a caller-provided workspace) that another member reads or writes;
+ * INVALID_ARG otherwise (read-read sharing is fine). The communicators must
+ * outlive the batch and must not run on their own, or in another batch,
+ * while a run of this one is in flight. Re-planning a member (any set call
+ * that discards its plan, hiccl_set_claim, hiccl_set_workspace) makes the
+ * batch stale: hiccl_batch_run then returns STATE. */
 int hiccl_batch_create(const hiccl_comm_t* comms, int n, int mode, hiccl_batch_t* out);
+/* Enqueue the batch on `stream` and return. STATE if a member changed since
+ * creation or the batch is in flight on another stream. */
 int hiccl_batch_run(hiccl_batch_t batch, void* stream);
 int hiccl_batch_wait(hiccl_batch_t batch);
 /* Completion times (ns, relative to the batch start) of each collective of
@@ -300,6 +327,20 @@ int hiccl_batch_wait(hiccl_batch_t batch);
  * has n entries. */
 int hiccl_batch_times(hiccl_batch_t batch, uint64_t* ns, int n);
 int hiccl_batch_destroy(hiccl_batch_t batch);
+
+/* Run `n` initialized communicators as one batch of form `mode`
+ * (hiccl_batch_mode) on `stream` and return at once: many collectives of
+ * one training or serving step issued together. The batch is built on the
+ * first call for this list of members and form (the same rules as
+ * hiccl_batch_create) and memoized, as the paper memoizes a collective's
+ * schedule when it is initialized (Sec. 5.2): later calls with the same
+ * list reuse its uploaded table. hiccl_wait on any member then waits for
+ * the whole batch (TIMEOUT if a dependency wait expired); a later hiccl_run
+ * of a member alone leaves the batch. The memoized batch is dropped when a
+ * member is re-planned or destroyed; at most 16 are kept (the oldest goes).
+ * Errors: as hiccl_batch_create / hiccl_batch_run; STATE if a member is in
+ * flight in another batch on another stream. */
+int hiccl_run_batch(const hiccl_comm_t* comms, int n, void* stream, int mode);
 
 /* Autotuner: times every (stripe, pipeline, tile) candidate on `stream`
  * (`reps` runs each after one warm-up) and re-initializes the communicator
@@ -340,10 +381,18 @@ int hiccl_server_stream(hiccl_server_t srv, uint64_t ticket, void** stream);
 /* Start an admitted request: enqueue `comm` (initialized) on its slot. It
  * sets the request's grid (hiccl_set_grid): the executor's full default
  * when no other request is running, else about 3 x compute units / slots
- * workgroups, so that concurrent requests overlap on the device. If the
- * launch fails, the ticket is released (slot and budget) and the error
- * returned. */
+ * workgroups, so that concurrent requests overlap on the device. With more
+ * than one slot a persistent-executor request claims its tiles from one
+ * queue for this launch (hiccl_set_claim's setting is left as it was), so
+ * its progress never depends on how many of its workgroups are resident
+ * beside other requests. If the launch fails, the ticket is released (slot
+ * and budget) and the error returned. */
 int hiccl_server_launch(hiccl_server_t srv, uint64_t ticket, hiccl_comm_t comm);
+/* Admit and launch in one call: the request's footprint is the union of the
+ * caller memory its primitives touch plus its workspace. Returns BUSY (with
+ * nothing charged) when no slot or budget is free right now; otherwise as
+ * hiccl_server_admit and hiccl_server_launch. */
+int hiccl_server_submit(hiccl_server_t srv, hiccl_comm_t comm, uint64_t* ticket);
 /* Retire finished requests (frees their slots and budget); non-blocking. */
 int hiccl_server_progress(hiccl_server_t srv);
 /* done = 1 once the request has finished; device_us = its time on the

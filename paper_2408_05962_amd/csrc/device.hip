@@ -1161,7 +1161,10 @@ struct DeviceState {
   bool launched = false;
   uint64_t ring_id = 0;                // device request ring holding this table's latest request (0: none)
   uint32_t ring_pos = 0;               // that request's position
+  hiccl_batch_s* batch = nullptr;      // hiccl_run_batch: the memoized batch this communicator last ran in
 };
+
+static void batch_cache_forget(DeviceState* s);
 
 void device_state_set_spin_limit(DeviceState* s, uint32_t polls) {
   if (s) s->exe.spin_limit = polls;
@@ -1174,6 +1177,7 @@ static bool ring_request_wait(uint64_t ring_id, uint32_t pos);
 
 void device_state_free(DeviceState* s) {
   if (!s) return;
+  batch_cache_forget(s);   // memoized batches built on this table are stale from now on
   // a request that is still in a ring after the bounded wait keeps its tables: they are leaked, not freed
   // under a running kernel
   if (s->ring_id && !ring_request_wait(s->ring_id, s->ring_pos)) {
@@ -1442,6 +1446,8 @@ static int read_status(const Exe& ex, int* status) {
   return 0;
 }
 
+static bool batch_in_flight_elsewhere(const hiccl_batch_s* b, hipStream_t st);
+
 // Make sure a communicator's tables and workspace are on the device.
 static int ensure_device(Comm& c) {
   if (c.dev) return 0;
@@ -1488,13 +1494,38 @@ int hiccl_run(hiccl_comm_t comm, void* stream) {
     return fail(HICCL_ERR_STATE, "a run of this communicator is in flight on another stream");
   if (c.dev && c.dev->ring_id && ring_request_pending(c.dev->ring_id, c.dev->ring_pos))
     return fail(HICCL_ERR_STATE, "this communicator has a request in a device ring");
+  if (c.dev && c.dev->batch && batch_in_flight_elsewhere(c.dev->batch, st))
+    return fail(HICCL_ERR_STATE, "a batch run holding this communicator is in flight on another stream");
   if (int rc = ensure_device(c)) return rc;
   if (int rc = launch(c.dev->exe, st)) return rc;
   HIP_TRY(hipEventRecord(c.dev->ev, st));
   c.dev->last_stream = st;
   c.dev->launched = true;
+  c.dev->batch = nullptr;
   return HICCL_SUCCESS;
 }
+
+}  // extern "C"
+
+namespace hiccl {
+// hiccl_run with the persistent executor claiming from one tile queue for
+// this launch only (the uploaded table does not depend on the queue count).
+// One queue keeps the run's progress independent of how many of its
+// workgroups are resident, which matters when other kernels share the device.
+int run_one_queue(hiccl_comm_t comm, void* stream) {
+  if (!comm) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator");
+  Comm& c = comm->c;
+  if (!c.planned) return fail(HICCL_ERR_STATE, "call hiccl_init before hiccl_run");
+  if (int rc = ensure_device(c)) return rc;
+  const uint32_t q = c.dev->exe.queues;
+  c.dev->exe.queues = 1;
+  const int rc = hiccl_run(comm, stream);
+  c.dev->exe.queues = q;
+  return rc;
+}
+}  // namespace hiccl
+
+extern "C" {
 
 int hiccl_set_grid(hiccl_comm_t comm, int grid) {
   if (!comm) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator");
@@ -1513,6 +1544,7 @@ int hiccl_set_grid(hiccl_comm_t comm, int grid) {
 int hiccl_wait(hiccl_comm_t comm) {
   if (!comm) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator");
   Comm& c = comm->c;
+  if (c.dev && c.dev->batch) return hiccl_batch_wait(c.dev->batch);   // last ran through hiccl_run_batch
   if (!c.dev || !c.dev->launched) return HICCL_SUCCESS;
   HIP_TRY(hipEventSynchronize(c.dev->ev));
   int status = 0;
@@ -1539,9 +1571,15 @@ struct hiccl_batch_s {
   double clock_hz = 1e8;
   std::vector<hipEvent_t> stage_ev;      // staged form: start, then the end of every stage launch
   std::vector<int> last_stage;           // staged form: each collective's last stage
+  std::vector<hiccl::DeviceState*> devs; // each member's device tables when the batch was built
+  hipStream_t last_stream = nullptr;
 };
 
 namespace hiccl {
+static bool batch_in_flight_elsewhere(const hiccl_batch_s* b, hipStream_t st) {
+  return b->launched && b->last_stream != st && hipEventQuery(b->ev) == hipErrorNotReady;
+}
+
 static int batch_prepare(hiccl_batch_s* b) {
   std::vector<const Plan*> plans;
   std::vector<uint64_t> wsb;
@@ -1549,6 +1587,7 @@ static int batch_prepare(hiccl_batch_s* b) {
     if (int rc = ensure_device(c->c)) return rc;
     plans.push_back(&c->c.plan);
     wsb.push_back(uint64_t(reinterpret_cast<uintptr_t>(c->c.dev->ws)));
+    b->devs.push_back(c->c.dev);
   }
   const ExecCfg& x = b->comms[0]->c.exec;
   if (b->mode == HICCL_BATCH_PERSISTENT || b->mode == HICCL_BATCH_PERSISTENT_SJF) {
@@ -1615,10 +1654,13 @@ int hiccl_batch_create(const hiccl_comm_t* comms, int n, int mode, hiccl_batch_t
   if (!comms || n < 1 || !out) return fail(HICCL_ERR_INVALID_ARG, "batch needs at least one communicator");
   if (mode < HICCL_BATCH_PERSISTENT || mode > HICCL_BATCH_STAGED)
     return fail(HICCL_ERR_INVALID_ARG, "bad batch mode");
+  std::vector<const Comm*> members;
   for (int i = 0; i < n; ++i) {
     if (!comms[i]) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator in batch");
     if (!comms[i]->c.planned) return fail(HICCL_ERR_STATE, "batch members must be initialized");
+    members.push_back(&comms[i]->c);
   }
+  if (int rc = batch_members_disjoint(members)) return rc;
   auto* b = new hiccl_batch_s;
   b->comms.assign(comms, comms + n);
   b->mode = mode;
@@ -1633,6 +1675,10 @@ int hiccl_batch_create(const hiccl_comm_t* comms, int n, int mode, hiccl_batch_t
 int hiccl_batch_run(hiccl_batch_t b, void* stream) {
   if (!b) return fail(HICCL_ERR_INVALID_ARG, "NULL batch");
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  for (size_t i = 0; i < b->comms.size(); ++i)
+    if (b->comms[i]->c.dev != b->devs[i])
+      return fail(HICCL_ERR_STATE, "a batch member was re-planned or changed since the batch was built");
+  if (batch_in_flight_elsewhere(b, st)) return fail(HICCL_ERR_STATE, "this batch is in flight on another stream");
   if (b->mode == HICCL_BATCH_PERSISTENT || b->mode == HICCL_BATCH_PERSISTENT_SJF) {
     if (int rc = launch(b->merged, st)) return rc;
   } else if (b->mode == HICCL_BATCH_STAGED) {
@@ -1683,6 +1729,7 @@ int hiccl_batch_run(hiccl_batch_t b, void* stream) {
   }
   HIP_TRY(hipEventRecord(b->ev, st));
   b->launched = true;
+  b->last_stream = st;
   return HICCL_SUCCESS;
 }
 
@@ -1751,6 +1798,77 @@ int hiccl_batch_destroy(hiccl_batch_t b) {
     if (b->branch[k]) (void)hipStreamDestroy(b->branch[k]);
   if (b->ev) (void)hipEventDestroy(b->ev);
   delete b;
+  return HICCL_SUCCESS;
+}
+
+}  // extern "C"
+
+// hiccl_run_batch: batches memoized by (members, form), as the paper memoizes
+// a collective's schedule at initialization (Sec. 5.2). An entry is dropped
+// when any member's device tables are freed (re-planned or destroyed), and
+// the oldest entry goes when the cache is full.
+namespace hiccl {
+struct BatchEntry {
+  std::vector<hiccl_comm_t> comms;
+  int mode;
+  hiccl_batch_t batch;
+};
+static std::mutex g_batch_mu;
+static std::vector<BatchEntry> g_batches;
+constexpr size_t kBatchCache = 16;
+
+static void batch_cache_drop(size_t i) {   // g_batch_mu held
+  hiccl_batch_t b = g_batches[i].batch;
+  for (size_t m = 0; m < b->comms.size(); ++m)
+    if (b->devs[m] && b->devs[m]->batch == b) b->devs[m]->batch = nullptr;
+  g_batches.erase(g_batches.begin() + long(i));
+  hiccl_batch_destroy(b);
+}
+
+static void batch_cache_forget(DeviceState* s) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  for (size_t i = g_batches.size(); i-- > 0;) {
+    const auto& d = g_batches[i].batch->devs;
+    if (std::find(d.begin(), d.end(), s) == d.end()) continue;
+    // the freed table's own back pointer goes with it; the others are cleared by the drop
+    for (DeviceState*& x : g_batches[i].batch->devs)
+      if (x == s) x = nullptr;
+    batch_cache_drop(i);
+  }
+}
+}  // namespace hiccl
+
+extern "C" {
+
+int hiccl_run_batch(const hiccl_comm_t* comms, int n, void* stream, int mode) {
+  if (!comms || n < 1) return fail(HICCL_ERR_INVALID_ARG, "batch needs at least one communicator");
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  hiccl_batch_t b = nullptr;
+  for (size_t i = 0; i < g_batches.size() && !b; ++i) {
+    const BatchEntry& e = g_batches[i];
+    if (e.mode != mode || e.comms.size() != size_t(n) || !std::equal(e.comms.begin(), e.comms.end(), comms)) continue;
+    bool fresh = true;
+    for (int m = 0; m < n; ++m) fresh = fresh && comms[m]->c.dev == e.batch->devs[m];
+    if (fresh) {
+      b = e.batch;
+    } else {
+      batch_cache_drop(i);
+      break;
+    }
+  }
+  if (!b) {
+    // a member that last ran in another memoized batch must not be in flight there
+    for (int m = 0; m < n; ++m)
+      if (comms[m] && comms[m]->c.dev && comms[m]->c.dev->batch &&
+          batch_in_flight_elsewhere(comms[m]->c.dev->batch, st))
+        return fail(HICCL_ERR_STATE, "a member is in flight in another batch on another stream");
+    if (int rc = hiccl_batch_create(comms, n, mode, &b)) return rc;
+    if (g_batches.size() >= kBatchCache) batch_cache_drop(0);
+    g_batches.push_back({std::vector<hiccl_comm_t>(comms, comms + n), mode, b});
+  }
+  if (int rc = hiccl_batch_run(b, stream)) return rc;
+  for (int m = 0; m < n; ++m) comms[m]->c.dev->batch = b;
   return HICCL_SUCCESS;
 }
 

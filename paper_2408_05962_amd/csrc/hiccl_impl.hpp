@@ -154,6 +154,9 @@ int build_plan(Comm& c);
 void order_and_tile(Plan& p, int order, size_t tile_bytes);
 uint64_t tile_elems_for(size_t tile_bytes, int dtype);
 int hier_depth(int a, int b, const std::vector<int>& h);
+uint64_t comm_footprint(const Comm& c);
+int run_one_queue(hiccl_comm_t comm, void* stream);   // device.hip
+int batch_members_disjoint(const std::vector<const Comm*>& comms);
 
 }  // namespace hiccl
 

@@ -1072,6 +1072,107 @@ static int add_prim(hiccl_comm_t comm, int kind, const hiccl_buf_t* send, const 
   return HICCL_SUCCESS;
 }
 
+}  // extern "C"
+
+namespace hiccl {
+
+// Caller memory a communicator touches: the union of its primitives' ranges
+// (data and fp8 scales), plus the workspace the plan needs. This is what a
+// request keeps resident while it is served.
+uint64_t comm_footprint(const Comm& c) {
+  std::vector<Range> all, one;
+  for (const Prim& p : c.prims) {
+    if (p.count == 0 || p.leaves.empty()) continue;
+    prim_ranges(c, p, one);
+    all.insert(all.end(), one.begin(), one.end());
+  }
+  std::sort(all.begin(), all.end(), [](const Range& a, const Range& b) { return a.lo < b.lo; });
+  uint64_t total = 0, lo = 0, hi = 0;
+  bool open = false;
+  for (const Range& r : all) {
+    if (r.hi <= r.lo) continue;
+    if (open && r.lo <= hi) {
+      hi = std::max(hi, r.hi);
+      continue;
+    }
+    if (open) total += hi - lo;
+    lo = r.lo;
+    hi = r.hi;
+    open = true;
+  }
+  if (open) total += hi - lo;
+  return total + (c.planned ? c.plan.ws_bytes : 0);
+}
+
+// Members of one batch run at the same time with no ordering between them,
+// so their memory must not conflict: no communicator twice (one workspace,
+// one set of counters), and no member may write caller memory that another
+// member reads or writes. Read-read sharing is allowed. A caller-provided
+// workspace counts as memory its member writes. One sweep over all ranges
+// sorted by start, keeping for reads and for writes the furthest end reached
+// by the two members that reach furthest.
+int batch_members_disjoint(const std::vector<const Comm*>& comms) {
+  for (size_t a = 0; a < comms.size(); ++a)
+    for (size_t b = a + 1; b < comms.size(); ++b)
+      if (comms[a] == comms[b]) return fail(HICCL_ERR_INVALID_ARG, "a communicator appears twice in one batch");
+  struct Tagged {
+    Range r;
+    int member;
+  };
+  std::vector<Tagged> all;
+  std::vector<Range> one;
+  for (size_t m = 0; m < comms.size(); ++m) {
+    const Comm& c = *comms[m];
+    for (const Prim& p : c.prims) {
+      if (p.count == 0 || p.leaves.empty()) continue;
+      prim_ranges(c, p, one);
+      for (const Range& r : one) all.push_back({r, int(m)});
+    }
+    if (c.user_ws && c.planned && c.plan.ws_bytes) {
+      const uint64_t w = uint64_t(reinterpret_cast<uintptr_t>(c.user_ws));
+      all.push_back({Range{0, w, w + c.plan.ws_bytes, true}, int(m)});
+    }
+  }
+  std::sort(all.begin(), all.end(), [](const Tagged& a, const Tagged& b) { return a.r.lo < b.r.lo; });
+  struct Reach {
+    uint64_t hi[2] = {0, 0};
+    int member[2] = {-1, -1};
+    void add(uint64_t h, int m) {
+      if (m == member[0]) {
+        hi[0] = std::max(hi[0], h);
+      } else if (m == member[1]) {
+        hi[1] = std::max(hi[1], h);
+        if (hi[1] > hi[0]) {
+          std::swap(hi[0], hi[1]);
+          std::swap(member[0], member[1]);
+        }
+      } else if (h > hi[0]) {
+        hi[1] = hi[0];
+        member[1] = member[0];
+        hi[0] = h;
+        member[0] = m;
+      } else if (h > hi[1]) {
+        hi[1] = h;
+        member[1] = m;
+      }
+    }
+    uint64_t other_than(int m) const { return member[0] != m ? hi[0] : hi[1]; }
+  } reads, writes;
+  for (const Tagged& t : all) {
+    if (t.r.hi <= t.r.lo) continue;
+    const bool hit = writes.other_than(t.member) > t.r.lo || (t.r.write && reads.other_than(t.member) > t.r.lo);
+    if (hit)
+      return fail(HICCL_ERR_INVALID_ARG,
+                  "batch members conflict: one writes memory that another reads or writes (they run unordered)");
+    (t.r.write ? writes : reads).add(t.r.hi, t.member);
+  }
+  return HICCL_SUCCESS;
+}
+
+}  // namespace hiccl
+
+extern "C" {
+
 int hiccl_add_multicast(hiccl_comm_t comm, const hiccl_buf_t* send, const hiccl_buf_t* recv, size_t count, int root,
                         const int* leaves, int nleaves) {
   return add_prim(comm, 0, send, recv, count, root, leaves, nleaves, HICCL_SUM);

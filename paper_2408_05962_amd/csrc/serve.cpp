@@ -134,10 +134,24 @@ int hiccl_server_launch(hiccl_server_t s, uint64_t ticket, hiccl_comm_t comm) {
   if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess ||
       hipEventRecord(r.start, st) != hipSuccess)
     return give_up(fail(HICCL_ERR_HIP, "request events"));
-  if (int rc = hiccl_run(comm, st)) return give_up(rc);
+  // with several slots any request may come to share the device with others while it runs, so the
+  // persistent executor claims from one tile queue: progress then holds however many of its
+  // workgroups are resident (the communicator's own claim setting is left as it was)
+  const int rc = s->streams.size() > 1 ? run_one_queue(comm, st) : hiccl_run(comm, st);
+  if (rc) return give_up(rc);
   if (hipEventRecord(r.stop, st) != hipSuccess) return give_up(fail(HICCL_ERR_HIP, "request event record"));
   r.launched = true;
   r.comm = comm;
+  return HICCL_SUCCESS;
+}
+
+int hiccl_server_submit(hiccl_server_t s, hiccl_comm_t comm, uint64_t* ticket) {
+  if (!s || !comm || !ticket) return fail(HICCL_ERR_INVALID_ARG, "NULL argument");
+  if (!comm->c.planned) return fail(HICCL_ERR_STATE, "call hiccl_init before submitting");
+  uint64_t t = 0;
+  if (int rc = hiccl_server_admit(s, size_t(comm_footprint(comm->c)), &t)) return rc;
+  if (int rc = hiccl_server_launch(s, t, comm)) return rc;   // a failed launch releases the ticket
+  *ticket = t;
   return HICCL_SUCCESS;
 }
 

@@ -94,6 +94,7 @@ def lib():
             "hiccl_batch_wait": [vp],
             "hiccl_batch_times": [vp, C.POINTER(u64), i],
             "hiccl_batch_destroy": [vp],
+            "hiccl_run_batch": [C.POINTER(vp), i, vp, i],
             "hiccl_autotune": [vp, pi, i, pi, i, C.POINTER(sz), i, i, vp, pi, pi, C.POINTER(sz),
                                C.POINTER(C.c_double)],
             "hiccl_autotune_model": [vp, pi, i, pi, i, C.POINTER(sz), i, i, i, i, vp, pi, pi, C.POINTER(sz),
@@ -102,6 +103,7 @@ def lib():
             "hiccl_server_admit": [vp, sz, C.POINTER(u64)],
             "hiccl_server_stream": [vp, u64, C.POINTER(vp)],
             "hiccl_server_launch": [vp, u64, vp],
+            "hiccl_server_submit": [vp, vp, C.POINTER(u64)],
             "hiccl_server_progress": [vp],
             "hiccl_server_poll": [vp, u64, pi, C.POINTER(C.c_double)],
             "hiccl_server_drain": [vp],
@@ -327,6 +329,14 @@ class Batch:
             pass
 
 
+def run_batch(comms, stream=None, mode="persistent"):
+    """Run initialized communicators as one memoized batch (hiccl_run_batch); ``comm.wait()`` on any member
+    waits for the whole batch."""
+    comms = list(comms)
+    arr = (C.c_void_p * len(comms))(*[c.h for c in comms])
+    return check(lib().hiccl_run_batch(arr, len(comms), stream_handle(stream), BATCH.get(mode, mode)))
+
+
 def autotune(comm: Comm, stripes, pipes, tiles, reps=3, stream=None):
     s, ns = _ints(stripes)
     p, np_ = _ints(pipes)
@@ -376,6 +386,15 @@ class Server:
         """A ticket, or None when the request must wait (no slot or budget free now)."""
         t = C.c_uint64()
         rc = lib().hiccl_server_admit(self.h, int(footprint), C.byref(t))
+        if rc == ERR_BUSY:
+            return None
+        check(rc)
+        return t.value
+
+    def submit(self, comm: Comm):
+        """Admit (footprint computed by the library) and launch in one call; None when the request must wait."""
+        t = C.c_uint64()
+        rc = lib().hiccl_server_submit(self.h, comm.h, C.byref(t))
         if rc == ERR_BUSY:
             return None
         check(rc)

@@ -337,3 +337,96 @@ def test_share_rank_is_validated(hc):
     c.set_share(3)
     c.set_share(-1)
     c.close()
+
+
+def _copy_comm(hc, src, dst, n=64):
+    """A one-hop communicator: rank 0's `src` to rank 1's `dst` (host addresses; nothing is launched)."""
+    c = hc.Comm(2, "float32")
+    c.add_multicast([src, None], [None, dst], n, 0, [1])
+    c.init()
+    return c
+
+
+def test_batch_members_must_be_disjoint(hc):
+    """Batch members run unordered: a communicator twice, or one member writing memory another reads or
+    writes, is rejected before anything touches the device. Read-read sharing passes the check."""
+    import ctypes as C
+    lib = hc.lib()
+    a, b, c_, d = (np.zeros(64, np.float32) for _ in range(4))
+    x = _copy_comm(hc, a, b)
+    y_rw = _copy_comm(hc, b, c_)          # reads what x writes
+    y_ww = _copy_comm(hc, d, b)           # writes what x writes
+    y_rr = _copy_comm(hc, a, c_)          # reads what x reads: allowed
+    y_half = hc.Comm(2, "float32")        # writes only the second half of b: still overlaps
+    y_half.add_multicast([d, None], [None, b[32:]], 32, 0, [1])
+    y_half.init()
+    y_next = hc.Comm(2, "float32")        # writes right after b's range ends: no overlap
+    e = np.zeros(128, np.float32)
+    x2 = _copy_comm(hc, a, e[:64])
+    y_next.add_multicast([d, None], [None, e[64:]], 64, 0, [1])
+    y_next.init()
+
+    def create(*cs):
+        arr = (C.c_void_p * len(cs))(*[q.h for q in cs])
+        h = C.c_void_p()
+        rc = lib.hiccl_batch_create(arr, len(cs), 0, C.byref(h))
+        if rc == 0:
+            lib.hiccl_batch_destroy(h)
+        return rc
+
+    assert create(x, x) == hc.ERR_INVALID_ARG
+    assert create(x, y_rw) == hc.ERR_INVALID_ARG
+    assert create(y_rw, x) == hc.ERR_INVALID_ARG
+    assert create(x, y_ww) == hc.ERR_INVALID_ARG
+    assert create(x, y_half) == hc.ERR_INVALID_ARG
+    assert create(y_rr, y_half, x) == hc.ERR_INVALID_ARG
+    # disjoint members get past the check (on a host without a GPU the device upload then fails)
+    assert create(x, y_rr) != hc.ERR_INVALID_ARG
+    assert create(x2, y_next) != hc.ERR_INVALID_ARG
+    # the memoized form applies the same rule
+    arr = (C.c_void_p * 2)(x.h, y_ww.h)
+    assert lib.hiccl_run_batch(arr, 2, None, 0) == hc.ERR_INVALID_ARG
+    for q in (x, y_rw, y_ww, y_rr, y_half, y_next, x2):
+        q.close()
+
+
+def test_batch_caller_workspaces_must_not_overlap(hc):
+    """A caller-provided workspace is memory its member writes."""
+    import ctypes as C
+    lib = hc.lib()
+    p, n = 4, 256
+    sends = [np.zeros(n, np.float32) for _ in range(2 * p)]
+    recvs = [np.zeros(n, np.float32) for _ in range(2 * p)]
+    cs = []
+    for k in range(2):
+        c = hc.Comm(p, "float32")
+        c.add_reduction(sends[k * p:(k + 1) * p], recvs[k * p:(k + 1) * p], n, list(range(p)), 0)
+        c.set_hierarchy([2, 2])
+        c.init()
+        cs.append(c)
+    ws = np.zeros(4 * cs[0].workspace_size() // 4 + 1024, np.float32)
+    base = (ws.ctypes.data + 255) // 256 * 256
+    cs[0].set_workspace(base, cs[0].workspace_size())
+    cs[1].set_workspace(base, cs[1].workspace_size())        # the same memory
+    arr = (C.c_void_p * 2)(cs[0].h, cs[1].h)
+    h = C.c_void_p()
+    assert lib.hiccl_batch_create(arr, 2, 0, C.byref(h)) == hc.ERR_INVALID_ARG
+    for c in cs:
+        c.close()
+
+
+def test_run_batch_and_submit_argument_errors(hc):
+    import ctypes as C
+    lib = hc.lib()
+    assert lib.hiccl_run_batch(None, 1, None, 0) == hc.ERR_INVALID_ARG
+    arr = (C.c_void_p * 1)(None)
+    assert lib.hiccl_run_batch(arr, 0, None, 0) == hc.ERR_INVALID_ARG
+    assert lib.hiccl_run_batch(arr, 1, None, 0) == hc.ERR_INVALID_ARG          # NULL member
+    c = hc.Comm(2, "float32")
+    a, b = np.zeros(8, np.float32), np.zeros(8, np.float32)
+    c.add_multicast([a, None], [None, b], 8, 0, [1])
+    arr = (C.c_void_p * 1)(c.h)
+    assert lib.hiccl_run_batch(arr, 1, None, 0) == hc.ERR_STATE                # not initialized
+    t = C.c_uint64()
+    assert lib.hiccl_server_submit(None, c.h, C.byref(t)) == hc.ERR_INVALID_ARG
+    c.close()

@@ -113,3 +113,44 @@ def test_scaled_error_metric():
     assert C.scaled_error(got, exact, scale) == pytest.approx(1e-6)
     rep = C.error_report(got, exact, scale)
     assert rep["max_abs"] == pytest.approx(4e-6)
+
+
+def test_error_report_hand_values():
+    """Every field of the error report against values worked out by hand.
+
+    exact = (1, -2, 0, 1e-4), scale = (1, 2, 4, 1), errors (1e-6, -4e-6, 4e-6, 1e-6):
+      * well conditioned where |exact| >= 1e-3 * scale: elements 0 and 1 only, so the plain relative
+        error is max(1e-6 / 1, 4e-6 / 2) = 2e-6 (element 3 would give 1e-2, element 2 a division by 0);
+      * normwise = ||err||_2 / ||exact||_2 = sqrt(34e-12) / sqrt(5 + 1e-8);
+      * scaled = max |err| / max(|exact|, scale) = max(1e-6, 2e-6, 1e-6, 1e-6) = 2e-6.
+    An infinity-norm or 1-norm in place of the 2-norm gives 2e-6 or 3.3e-6, not 2.61e-6."""
+    exact = np.array([1.0, -2.0, 0.0, 1e-4])
+    scale = np.array([1.0, 2.0, 4.0, 1.0])
+    err = np.array([1e-6, -4e-6, 4e-6, 1e-6])
+    rep = C.error_report(exact + err, exact, scale)
+    assert rep["max_abs"] == pytest.approx(4e-6, rel=1e-9)
+    assert rep["scaled"] == pytest.approx(2e-6, rel=1e-9)
+    assert rep["rel_well_conditioned"] == pytest.approx(2e-6, rel=1e-9)
+    assert rep["normwise"] == pytest.approx(np.sqrt(34e-12 / (5 + 1e-8)), rel=1e-9)
+    assert rep["normwise"] == pytest.approx(2.6076809e-6, rel=1e-6)
+
+
+def test_error_report_special_cases():
+    # an exact result of all zeros: the normwise error falls back to the absolute 2-norm (3-4-5)
+    rep = C.error_report(np.array([3e-6, -4e-6]), np.zeros(2), np.ones(2))
+    assert rep["normwise"] == pytest.approx(5e-6, rel=1e-9)
+    assert rep["rel_well_conditioned"] == 0.0           # nothing is well conditioned
+    assert rep["scaled"] == pytest.approx(4e-6, rel=1e-9)
+    # the whole array is one vector: a (2, 2) block reports what its flattening reports, whatever axis
+    ex = np.array([[1.0, 2.0], [3.0, 4.0]])
+    got = ex + np.array([[1e-3, 0.0], [0.0, -2e-3]])
+    sc = np.abs(ex)
+    r2 = C.error_report(got, ex, sc)
+    r1 = C.error_report(got.ravel(), ex.ravel(), sc.ravel())
+    assert r2 == r1
+    assert r2["normwise"] == pytest.approx(np.sqrt(5e-6 / 30.0), rel=1e-9)
+    assert r2["rel_well_conditioned"] == pytest.approx(1e-3, rel=1e-9)
+    # exact agreement reports zero everywhere
+    assert all(v == 0.0 for v in C.error_report(ex, ex, sc).values())
+    # empty input
+    assert all(v == 0.0 for v in C.error_report(np.zeros(0), np.zeros(0), np.zeros(0)).values())

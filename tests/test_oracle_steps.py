@@ -95,3 +95,52 @@ def test_single_leaf_reduction_is_copy():
     r = S.reduction([0], 1, 3, {0: ("a", 0)}, {1: ("b", 0)}, "sum")
     mem = S.run(S.Memory(bufs), [[r]])
     assert list(mem.result("b", np.int32)) == [5, 6, 7]
+
+
+def test_max_min_reductions_hand_values():
+    """max and min reductions of the interpreter on hand-checked values, with negatives (int32 and
+    float32), a fenced second step that reads the first step's results, and a one-leaf max (a copy)."""
+    s = {"s0": np.array([3, -7, 0, 1000], np.int32), "s1": np.array([-1, 5, 2, -1000], np.int32),
+         "s2": np.array([2, 2, -9, 999], np.int32)}
+    bufs = dict(s, ya=np.zeros(4, np.int32), yb=np.zeros(4, np.int32), yc=np.zeros(4, np.int32),
+                yd=np.zeros(4, np.int32))
+    send = {0: ("s0", 0), 1: ("s1", 0), 2: ("s2", 0)}
+    r_max = S.reduction([0, 1, 2], 0, 4, send, {0: ("ya", 0)}, "max")
+    r_min = S.reduction([2, 1, 0], 1, 4, send, {1: ("yb", 0)}, "min")
+    # second step: max over the two results of the first step (rank 0 holds ya, rank 1 holds yb)
+    r_mix = S.reduction([0, 1], 2, 4, {0: ("ya", 0), 1: ("yb", 0)}, {2: ("yc", 0)}, "max")
+    r_one = S.reduction([1], 0, 4, {1: ("s1", 0)}, {0: ("yd", 0)}, "min")
+    mem = S.run(S.Memory(bufs), [[r_max, r_min, r_one], [r_mix]])
+    assert list(mem.result("ya", np.int32)) == [3, 5, 2, 1000]
+    assert list(mem.result("yb", np.int32)) == [-1, -7, -9, -1000]
+    assert list(mem.result("yc", np.int32)) == [3, 5, 2, 1000]
+    assert list(mem.result("yd", np.int32)) == [-1, 5, 2, -1000]
+    f = {"a": np.array([-0.5, 2.25, -3.0], np.float32), "b": np.array([-0.25, -2.5, 1.5], np.float32),
+         "m": np.zeros(3, np.float32), "n": np.zeros(3, np.float32)}
+    fs = {0: ("a", 0), 1: ("b", 0)}
+    mem = S.run(S.Memory(f), [[S.reduction([0, 1], 0, 3, fs, {0: ("m", 0)}, "max"),
+                               S.reduction([0, 1], 1, 3, fs, {1: ("n", 0)}, "min")]])
+    assert list(mem.result("m", np.float32)) == [-0.25, 2.25, 1.5]
+    assert list(mem.result("n", np.float32)) == [-0.5, -2.5, -3.0]
+
+
+@pytest.mark.parametrize("name", ["reduce", "reduce_scatter", "all_reduce"])
+@pytest.mark.parametrize("op", ["max", "min"])
+@pytest.mark.parametrize("form", ["single", "multi"])
+def test_max_min_compositions_brute_force(name, op, form):
+    """Composition rows with max / min against a brute-force loop over every element and rank."""
+    p, d = 3, 2
+    rng = np.random.default_rng(11)
+    sends = [rng.integers(-50, 51, d * p).astype(np.int32) for _ in range(p)]
+    steps = S.compose(name, p, d, op=op, form=form)
+    mem = S.run(S.Memory(S.buffers_for(name, p, d, sends, form)), steps)
+    pick = max if op == "max" else min
+    full = [pick(int(sends[r][e]) for r in range(p)) for e in range(d * p)]
+    if name == "reduce":
+        assert list(mem.result("y0", np.int32)) == full
+    elif name == "reduce_scatter":
+        for r in range(p):
+            assert list(mem.result(f"y{r}", np.int32)) == full[r * d:(r + 1) * d]
+    else:
+        for r in range(p):
+            assert list(mem.result(f"y{r}", np.int32)) == full
