@@ -200,14 +200,7 @@ def tree_order_payload(name, payloads, h, s, ring=1):
     def striped(vals, root, m):
         if ring > 1:
             return _striped_ring(vals, root, m, h, s, ring, align, _node(dtype), lambda parts: _concat(parts, dtype))
-        own = OT.stripe_owners(root, range(p), h, s)
-        if own is None:
-            return OT.tree_reduce(vals, range(p), root, h, _node(dtype))
-        parts = []
-        for t, (off, ln) in enumerate(OT.split(m, s, align)):
-            sub = {r: v[off:off + ln] for r, v in vals.items()}
-            parts.append(OT.tree_reduce(sub, range(p), own[t], h, _node(dtype)))
-        return _concat(parts, dtype)
+        return chunk_reduce(vals, root, m, h, s, dtype)
 
     vals = dict(enumerate(payloads))
     if name == "reduce":
@@ -218,3 +211,23 @@ def tree_order_payload(name, payloads, h, s, ring=1):
         return out
     full = _concat([out[j] for j in range(p)], dtype)
     return {r: full for r in range(p)}
+
+
+def chunk_reduce(vals, root, m, h, s, dtype, pool=None):
+    """R(all ranks, root) over m elements in the tree order of the factorization, per stripe when the
+    reduction is striped. float32 operands are summed left to right in float32; payload operands go
+    through the oracle's widen / sum / narrow node. `pool` (an executor) runs the stripes concurrently."""
+    p = len(vals)
+    align = ALIGN[dtype]
+    node = OT.sum_f32 if dtype == "float32" else _node(dtype)
+    own = OT.stripe_owners(root, range(p), h, s)
+    if own is None:
+        return OT.tree_reduce(vals, range(p), root, h, node)
+    jobs = []
+    for t, (off, ln) in enumerate(OT.split(m, s, align)):
+        jobs.append(({r: v[off:off + ln] for r, v in vals.items()}, own[t]))
+    run = (lambda f, xs: list(pool.map(f, xs))) if pool is not None else (lambda f, xs: [f(x) for x in xs])
+    parts = run(lambda job: OT.tree_reduce(job[0], range(p), job[1], h, node), jobs)
+    if dtype == "float32":
+        return np.concatenate(parts)
+    return _concat(parts, dtype)

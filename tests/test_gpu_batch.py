@@ -204,3 +204,41 @@ def test_batch_512_full_size(torch_cuda):
         b.close()
     for it in items:
         it["c"].close()
+
+
+@pytest.mark.parametrize("mode", ["persistent", "graph"])
+def test_run_batch_memoized(torch_cuda, mode):
+    """hiccl_run_batch: the members run as one memoized batch; waiting on any member waits for all; every
+    result is bit-identical to the collective run alone. A member run alone in between leaves the batch,
+    and the next call runs it in the batch again."""
+    torch = torch_cuda
+    from paper_2408_05962_amd import run_batch
+    items = _mix(torch, 12, seed=23)
+    st = torch.cuda.current_stream()
+    alone = []
+    for it in items:
+        it["R"].zero_()
+        it["comm"].run(st)
+        it["comm"].wait()
+        torch.cuda.synchronize()
+        alone.append(it["R"].cpu().numpy().copy())
+    comms = [it["comm"] for it in items]
+    for rep in range(3):
+        for it in items:
+            it["R"].zero_()
+        run_batch(comms, st, mode)
+        comms[(5 * rep) % len(comms)].wait()
+        torch.cuda.synchronize()
+        for k, it in enumerate(items):
+            got = it["R"].cpu().numpy()
+            assert np.array_equal(got.view(np.uint32), alone[k].view(np.uint32)), (mode, rep, k, it["name"])
+        if rep == 1:
+            it = items[3]
+            it["R"].zero_()
+            it["comm"].run(st)
+            it["comm"].wait()
+            torch.cuda.synchronize()
+            assert np.array_equal(it["R"].cpu().numpy().view(np.uint32), alone[3].view(np.uint32))
+    for k, it in enumerate(items):
+        H.check_result(it["name"], _got(it), it["sends"], it["dtype"], h=[2, 4], s=it["s"])
+        it["comm"].close()

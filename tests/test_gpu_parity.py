@@ -387,3 +387,60 @@ def test_two_step_compositions(torch_cuda, name, h, s, m, mode):
         out = R.cpu().numpy()
         H.check_result(base, _got(base, out, p, p - 1), sends, "int32", root=p - 1)
     c.close()
+
+
+def _two_step_f32_expected(name, sends, h, s, root):
+    """Tree-order float32 result of a two-step row of Table 2: the reduction step is summed in the
+    oracle's tree order (per stripe), and the copy step moves its bits unchanged."""
+    p = len(sends)
+    if name in ("broadcast", "all_gather"):
+        return None                                             # pure data movement: checked exactly
+    if name == "reduce":                                        # Gather . Reduce-scatter
+        return {root: H.tree_order_f32("all_reduce", sends, h, s)[0]}
+    full = H.tree_order_f32("reduce", sends, h, s, root=root)[root]     # Reduce at the root first
+    if name == "reduce_scatter":                                # Scatter . Reduce
+        d = len(full) // p
+        return {j: full[j * d:(j + 1) * d] for j in range(p)}
+    return {r: full for r in range(p)}                          # all_reduce_bcast = Broadcast . Reduce
+
+
+@pytest.mark.parametrize("name", ["broadcast", "reduce", "all_gather", "reduce_scatter", "all_reduce_bcast"])
+@pytest.mark.parametrize("mode", ["persistent", "staged"])
+def test_two_step_compositions_float32(torch_cuda, name, mode):
+    """The two-step rows of Table 2 in float32 at {2,4,2}, stripe 4, pipeline 2, with a ragged chunk:
+    within the condition-scaled 1e-5 of the float64 definitions, and bit-identical to the oracle's
+    tree-order sums carried through the scratch buffer."""
+    torch = torch_cuda
+    from paper_2408_05962_amd import Comm
+    from paper_2408_05962_amd import collectives as CO
+    h, s, m = [2, 4, 2], 4, 2
+    p, root = 16, 15
+    d = 4096 + 3
+    base = "all_reduce" if name == "all_reduce_bcast" else name
+    sends = _host_inputs(base, p, d, "float32", zlib.crc32(f"two-f32{name}".encode()) % 1000)
+    S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+    R = torch.full((p, H.recv_len(base, p, d)), -7, dtype=torch.float32, device="cuda")
+    X = torch.zeros((p, d * p), dtype=torch.float32, device="cuda")
+    c = Comm(p, "float32")
+    CO.compose_multi(c, name, [S[r] for r in range(p)], [R[r] for r in range(p)], [X[r] for r in range(p)], d,
+                     root=root)
+    c.set_hierarchy(h)
+    c.set_stripe(s)
+    c.set_pipeline(m)
+    c.set_exec(mode)
+    c.set_spin_limit(1 << 20)
+    c.init()
+    exp = _two_step_f32_expected(name, sends, h, s, root)
+    for _ in range(2):
+        R.fill_(-7)
+        c.run(torch.cuda.current_stream())
+        c.wait()
+        torch.cuda.synchronize()
+        out = R.cpu().numpy()
+        got = _got(base, out, p, root)
+        H.check_result(base, got, sends, "float32", root=root)
+        if exp is not None:
+            for r, y in exp.items():
+                assert np.array_equal(got[r].view(np.uint32), y.view(np.uint32)), \
+                    f"{name} {mode} rank {r}: not the tree-order float32 sums"
+    c.close()

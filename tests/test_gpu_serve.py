@@ -148,3 +148,69 @@ def test_failed_launch_releases_and_timeouts_are_reported(torch_cuda):
     H.check_result("all_reduce", {r: out[r] for r in range(p)}, sends, "int32")
     srv.close()
     c.close()
+
+
+def test_submit_results_identical_alone_and_in_the_mix(torch_cuda):
+    """hiccl_server_submit: admission with the footprint the library computes (the caller memory a
+    request's primitives touch plus its workspace) and launch in one call. The templates keep the
+    default claim setting (8 queues): the server itself makes a launch beside others claim from one
+    queue. Every result is bit-identical to the request run alone; the budget and slots are never
+    exceeded."""
+    torch = torch_cuda
+    import synth
+    from paper_2408_05962_amd import Server
+    from paper_2408_05962_amd import collectives as CO
+    rng = synth.choice_stream(5, 9)
+    hiers = [[2, 4], [2, 4, 2], [4, 4]]
+    temps = []
+    for i in range(12):
+        name = H.SIX[(i + 2) % 6]
+        h = hiers[int(rng.integers(0, 3))]
+        p = int(np.prod(h))
+        dtype = "int32" if i % 2 == 0 else "float32"
+        d = int(rng.integers(1000, 20000))
+        sends = synth.rank_buffers(dtype, 22, i, p, H.send_len(name, p, d))
+        S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+        R = torch.zeros((p, H.recv_len(name, p, d)), dtype=S.dtype, device="cuda")
+        c = CO.make(name, p, dtype, [S[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=h,
+                    stripe=2, pipeline=2, tile_bytes=8192)
+        c.set_spin_limit(1 << 20)
+        temps.append({"c": c, "S": S, "R": R, "sends": sends, "name": name, "dtype": dtype, "h": h, "p": p,
+                      "foot": (S.numel() + R.numel()) * 4 + c.workspace_size()})
+    st = torch.cuda.current_stream()
+    alone = []
+    for tp in temps:
+        tp["R"].zero_()
+        tp["c"].run(st)
+        tp["c"].wait()
+        torch.cuda.synchronize()
+        alone.append(tp["R"].cpu().numpy().copy())
+        ranks = [0] if tp["name"] == "reduce" else range(tp["p"])
+        H.check_result(tp["name"], {r: alone[-1][r] for r in ranks}, tp["sends"], tp["dtype"], h=tp["h"], s=2)
+    for tp in temps:
+        tp["R"].zero_()
+    torch.cuda.synchronize()
+    budget = 2 * max(tp["foot"] for tp in temps)
+    srv = Server(budget, 4)
+    pending = list(range(len(temps)))
+    tickets = {}
+    while pending or tickets:
+        while pending:
+            tk = srv.submit(temps[pending[0]]["c"])
+            if tk is None:
+                break
+            tickets[tk] = pending.pop(0)
+        srv.progress()
+        used, running = srv.usage()
+        assert used <= budget and running <= 4
+        for tk in list(tickets):
+            done, _ = srv.poll(tk)
+            if done:
+                tickets.pop(tk)
+    srv.drain()
+    srv.close()
+    torch.cuda.synchronize()
+    for k, tp in enumerate(temps):
+        got = tp["R"].cpu().numpy()
+        assert np.array_equal(got.view(np.uint32), alone[k].view(np.uint32)), (k, tp["name"])
+        tp["c"].close()
