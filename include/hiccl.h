@@ -217,8 +217,34 @@ int hiccl_set_workspace(hiccl_comm_t comm, void* dptr, size_t bytes);
 int hiccl_run(hiccl_comm_t comm, void* stream);
 
 /* wait() of Listing 2: block the host until the last run's buffers may be
- * reused. Returns TIMEOUT if the executor gave up a dependency wait. */
+ * reused. Returns TIMEOUT if the executor gave up a dependency wait. After
+ * hiccl_run_static it synchronizes that run's stream and reads the status
+ * word in the device's static scratch (the last static run's on the device). */
 int hiccl_wait(hiccl_comm_t comm);
+
+/* Size of the static device scratch of hiccl_run_static: 64 MiB, held by
+ * every GPU the library runs on from its first such call until the
+ * process ends. */
+#define HICCL_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): hiccl_run
+ * without any allocation. The communicator's task table, dependency
+ * counters and workspace live in a static device array of
+ * HICCL_STATIC_SCRATCH_BYTES per GPU instead of library allocations; the
+ * caller still passes the input and output buffers (at registration).
+ * Each call copies the table (built on the host at the first call and kept
+ * with the communicator) into the array on `stream`, which also resets
+ * every counter, then launches the same kernels as hiccl_run; it calls no
+ * hipMalloc / hipFree and ignores a workspace set by hiccl_set_workspace.
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents: calls that overlap on one GPU (two streams, or the
+ * device request ring of a server) race and give undefined results, so the
+ * caller orders them. hiccl_wait follows the latest static run. Errors:
+ * STATE (not initialized, or a run of this communicator in flight on
+ * another stream), INVALID_ARG (the plan's workspace and tables need more
+ * than HICCL_STATIC_SCRATCH_BYTES; checked before any device call), HIP. */
+int hiccl_run_static(hiccl_comm_t comm, void* stream);
 
 /* Workgroups of the next runs (0 = the default of hiccl_set_exec), without re-planning.
  * A smaller grid lets several collectives share the device at once. */

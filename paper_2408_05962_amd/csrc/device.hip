@@ -1254,12 +1254,21 @@ static bool xcd_group(const std::vector<DevTask>& h, std::vector<uint2>& order, 
   return true;
 }
 
-static int upload(const std::vector<const Plan*>& plans, const std::vector<uint64_t>& ws_base, int mode, int grid,
-                  uint32_t spin_limit, bool with_times, Exe& ex, int queues = kMaxQueues,
-                  int batch = HICCL_CLAIM_BATCH, int merge = 0) {
-  int dev = 0;
-  HIP_TRY(hipGetDevice(&dev));
-  ex.device = dev;
+// Host image of a task table: what upload() copies to the device. Descriptors
+// of tasks with more than four operands point into `extra`; extra_fix lists
+// (task, offset into extra) pairs to patch once extra's device address is known.
+struct Image {
+  std::vector<DevTask> tasks;
+  std::vector<uint2> order;
+  std::vector<uint32_t> succ, comm_n, cnt;
+  std::vector<uint64_t> extra;
+  std::vector<std::pair<size_t, size_t>> extra_fix;
+};
+
+// Build the host image of the merged table of `plans` and fill the host-side
+// fields of `ex` (stage boundaries, launch shape); no device pointer is set.
+static int build_image(const std::vector<const Plan*>& plans, const std::vector<uint64_t>& ws_base, int mode,
+                       int grid, uint32_t spin_limit, Exe& ex, int queues, int batch, int merge, Image& img) {
   ex.mode = mode;
   ex.spin_limit = spin_limit;
   ex.ncomm = uint32_t(plans.size());
@@ -1289,10 +1298,14 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
   for (uint32_t i = 0; i < refs.size(); ++i) newidx[refs[i].plan][refs[i].idx] = i;
 
   size_t nt = refs.size();
-  std::vector<DevTask> h(nt);
-  std::vector<uint32_t> succ, tile_task, comm_n(plans.size(), 0);
-  std::vector<uint64_t> extra;
-  std::vector<std::pair<size_t, size_t>> extra_fix;   // (task, offset into extra) to patch
+  std::vector<DevTask>& h = img.tasks;
+  h.assign(nt, DevTask{});
+  std::vector<uint32_t>& succ = img.succ;
+  std::vector<uint32_t>& comm_n = img.comm_n;
+  std::vector<uint32_t> tile_task;
+  comm_n.assign(plans.size(), 0);
+  std::vector<uint64_t>& extra = img.extra;
+  std::vector<std::pair<size_t, size_t>>& extra_fix = img.extra_fix;
   int nstages = 0;
   for (size_t i = 0; i < nt; ++i) {
     const Task& t = plans[refs[i].plan]->tasks[refs[i].idx];
@@ -1344,7 +1357,8 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
   // position p on XCD p mod 8 (hiccl_staged), and the persistent executor deals position p to queue
   // p mod 8, served by the workgroups of XCD p mod 8 (claim_next). Any order inside a stage is
   // topological, since a task's predecessors all lie in earlier stages.
-  std::vector<uint2> order(tile_task.size());
+  std::vector<uint2>& order = img.order;
+  order.assign(tile_task.size(), uint2{});
   for (size_t tl = 0; tl < tile_task.size(); ++tl)
     order[tl] = make_uint2(tile_task[tl], uint32_t(tl - h[tile_task[tl]].first_tile));
   bool stage_sorted = true;
@@ -1361,35 +1375,55 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
     for (int s = 0; s < nstages; ++s)
       ex.stage_shared[s] = xcd_group(h, order, ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1], spread) ? 1 : 0;
 
+  // counters: pending | done | per-collective tasks left | control block
+  img.cnt.assign(2 * nt + plans.size() + kCtlWords, 0);
+  for (size_t p = 0; p < plans.size(); ++p) img.cnt[2 * nt + p] = comm_n[p];
+  ex.grid = std::min<int>(device_grid(grid), std::max<uint32_t>(1u, ex.ntiles));
+  ex.stage_grid = grid;
+  ex.queues = uint32_t(std::max(1, std::min<int>(queues, std::min<int>(kMaxQueues, ex.grid))));
+  ex.batch = uint32_t(std::max(1, batch));
+  return 0;
+}
+
+// Point the operand-array descriptors (tasks with more than four operands)
+// at `extra`'s device copy.
+static void patch_extra(Image& img, const uint64_t* d_extra) {
+  for (auto& f : img.extra_fix) {
+    const size_t k = img.tasks[f.first].meta >> 8;
+    img.tasks[f.first].src[0] = uint64_t(reinterpret_cast<uintptr_t>(d_extra + f.second));
+    img.tasks[f.first].src_sc[0] = uint64_t(reinterpret_cast<uintptr_t>(d_extra + f.second + k));
+  }
+}
+
+static int upload(const std::vector<const Plan*>& plans, const std::vector<uint64_t>& ws_base, int mode, int grid,
+                  uint32_t spin_limit, bool with_times, Exe& ex, int queues = kMaxQueues,
+                  int batch = HICCL_CLAIM_BATCH, int merge = 0) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  ex.device = dev;
+  Image img;
+  if (int rc = build_image(plans, ws_base, mode, grid, spin_limit, ex, queues, batch, merge, img)) return rc;
   auto alloc_copy = [&](void** dptr, const void* src, size_t bytes) -> int {
     HIP_TRY(hipMalloc(dptr, std::max<size_t>(bytes, 16)));
     if (bytes) HIP_TRY(hipMemcpy(*dptr, src, bytes, hipMemcpyHostToDevice));
     return 0;
   };
-  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_order), order.data(), order.size() * sizeof(uint2))) return rc;
-  if (!extra.empty()) {
-    if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_extra), extra.data(), extra.size() * 8)) return rc;
-    for (auto& f : extra_fix) {
-      size_t k = h[f.first].meta >> 8;
-      h[f.first].src[0] = uint64_t(reinterpret_cast<uintptr_t>(ex.d_extra + f.second));
-      h[f.first].src_sc[0] = uint64_t(reinterpret_cast<uintptr_t>(ex.d_extra + f.second + k));
-    }
+  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_order), img.order.data(), img.order.size() * sizeof(uint2)))
+    return rc;
+  if (!img.extra.empty()) {
+    if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_extra), img.extra.data(), img.extra.size() * 8)) return rc;
+    patch_extra(img, ex.d_extra);
   }
-  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_tasks), h.data(), h.size() * sizeof(DevTask))) return rc;
-  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_succ), succ.data(), succ.size() * 4)) return rc;
-  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_comm_ntasks), comm_n.data(), comm_n.size() * 4)) return rc;
-  size_t ncnt = 2 * nt + plans.size() + kCtlWords;
-  std::vector<uint32_t> cnt(ncnt, 0);
-  for (size_t p = 0; p < plans.size(); ++p) cnt[2 * nt + p] = comm_n[p];
-  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_cnt), cnt.data(), cnt.size() * 4)) return rc;
+  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_tasks), img.tasks.data(), img.tasks.size() * sizeof(DevTask)))
+    return rc;
+  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_succ), img.succ.data(), img.succ.size() * 4)) return rc;
+  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_comm_ntasks), img.comm_n.data(), img.comm_n.size() * 4))
+    return rc;
+  if (int rc = alloc_copy(reinterpret_cast<void**>(&ex.d_cnt), img.cnt.data(), img.cnt.size() * 4)) return rc;
   if (with_times) {
     HIP_TRY(hipMalloc(reinterpret_cast<void**>(&ex.d_times), (plans.size() + 1) * sizeof(unsigned long long)));
     HIP_TRY(hipMemset(ex.d_times, 0, (plans.size() + 1) * sizeof(unsigned long long)));
   }
-  ex.grid = std::min<int>(device_grid(grid), std::max<uint32_t>(1u, ex.ntiles));
-  ex.stage_grid = grid;
-  ex.queues = uint32_t(std::max(1, std::min<int>(queues, std::min<int>(kMaxQueues, ex.grid))));
-  ex.batch = uint32_t(std::max(1, batch));
   return 0;
 }
 
@@ -1447,6 +1481,7 @@ static int read_status(const Exe& ex, int* status) {
 }
 
 static bool batch_in_flight_elsewhere(const hiccl_batch_s* b, hipStream_t st);
+static int static_wait(Comm& c);   // hiccl_wait after hiccl_run_static (allocation-free entry point)
 
 // Make sure a communicator's tables and workspace are on the device.
 static int ensure_device(Comm& c) {
@@ -1502,6 +1537,7 @@ int hiccl_run(hiccl_comm_t comm, void* stream) {
   c.dev->last_stream = st;
   c.dev->launched = true;
   c.dev->batch = nullptr;
+  c.last_static = false;
   return HICCL_SUCCESS;
 }
 
@@ -1544,12 +1580,192 @@ int hiccl_set_grid(hiccl_comm_t comm, int grid) {
 int hiccl_wait(hiccl_comm_t comm) {
   if (!comm) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator");
   Comm& c = comm->c;
+  if (c.last_static) return static_wait(c);                          // last ran through hiccl_run_static
   if (c.dev && c.dev->batch) return hiccl_batch_wait(c.dev->batch);   // last ran through hiccl_run_batch
   if (!c.dev || !c.dev->launched) return HICCL_SUCCESS;
   HIP_TRY(hipEventSynchronize(c.dev->ev));
   int status = 0;
   if (int rc = read_status(c.dev->exe, &status)) return rc;
   if (status) return fail(HICCL_ERR_TIMEOUT, "executor gave up a dependency wait (spin limit reached)");
+  return HICCL_SUCCESS;
+}
+
+}  // extern "C"
+
+// ================================================== allocation-free entry point
+// Device memory of hiccl_run_static: the task table, the dependency counters
+// and the workspace of its runs live in this array instead of in library
+// allocations. Every GPU the library runs on holds its own copy until the
+// process ends. Host code never passes this name as an address: it asks the
+// runtime for each device's copy once (static_scratch) and uses that address.
+static __device__ __align__(256) unsigned char scratch[HICCL_STATIC_SCRATCH_BYTES];
+
+namespace hiccl {
+
+struct StaticState {
+  Exe ex;                            // non-owning: every pointer lies inside one device's scratch array
+  std::vector<unsigned char> blob;   // host image of the tables; copied to scratch + table_off on every run
+  uint64_t table_off = 0;
+  void* base = nullptr;              // the scratch address the image was built for
+  hipStream_t stream = nullptr;
+  bool launched = false;
+};
+
+void static_state_free(StaticState* s) {
+  if (!s) return;
+  // a copy from the host image may still be queued: let the device drain before the image goes
+  if (s->launched) (void)hipDeviceSynchronize();
+  delete s;
+}
+
+// Placement of a plan in the static scratch: workspace first, then the tables,
+// each section 256-byte aligned. Host arithmetic only (no device call).
+struct StaticLayout {
+  uint64_t tasks = 0, order = 0, succ = 0, extra = 0, comm_n = 0, cnt = 0, end = 0;
+};
+
+static uint64_t round256(uint64_t x) { return (x + 255) / 256 * 256; }
+
+static StaticLayout static_layout(const Plan& p) {
+  uint64_t nsucc = 0, nextra = 0, ntiles = 0;
+  for (const Task& t : p.tasks) {
+    nsucc += t.succs.size();
+    ntiles += t.ntiles;
+    if (t.src.size() > 4) nextra += 2 * t.src.size();
+  }
+  const uint64_t nt = p.tasks.size();
+  StaticLayout L;
+  uint64_t off = round256(p.ws_bytes);
+  L.tasks = off;
+  off = round256(off + nt * sizeof(DevTask));
+  L.order = off;
+  off = round256(off + ntiles * sizeof(uint2));
+  L.succ = off;
+  off = round256(off + nsucc * 4);
+  L.extra = off;
+  off = round256(off + nextra * 8);
+  L.comm_n = off;
+  off = round256(off + 4);
+  L.cnt = off;
+  L.end = round256(off + (2 * nt + 1 + kCtlWords) * 4);
+  return L;
+}
+
+// This device's address of the scratch array, asked of the runtime once per
+// device with that device current.
+static int static_scratch(void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(HICCL_ERR_UNSUPPORTED, "device index beyond 64");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(HICCL_ERR_HIP, std::string("address of the static scratch: ") + hipGetErrorString(e));
+    addr[dev] = ptr;
+  }
+  *out = addr[dev];
+  return 0;
+}
+
+// Build the host image of a plan placed at `base` (host allocations only).
+static int static_build(Comm& c, const StaticLayout& L, void* base, StaticState& s) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  s.ex.device = dev;
+  const uint64_t b = uint64_t(reinterpret_cast<uintptr_t>(base));
+  Image img;
+  if (int rc = build_image({&c.plan}, {b}, c.exec.mode, c.exec.grid, c.exec.spin_limit, s.ex, c.exec.queues,
+                           c.exec.batch, 0, img))
+    return rc;
+  unsigned char* B = static_cast<unsigned char*>(base);
+  s.ex.d_tasks = reinterpret_cast<DevTask*>(B + L.tasks);
+  s.ex.d_order = reinterpret_cast<uint2*>(B + L.order);
+  s.ex.d_succ = reinterpret_cast<uint32_t*>(B + L.succ);
+  s.ex.d_extra = img.extra.empty() ? nullptr : reinterpret_cast<uint64_t*>(B + L.extra);
+  s.ex.d_comm_ntasks = reinterpret_cast<uint32_t*>(B + L.comm_n);
+  s.ex.d_cnt = reinterpret_cast<uint32_t*>(B + L.cnt);
+  s.ex.d_times = nullptr;
+  if (!img.extra.empty()) patch_extra(img, s.ex.d_extra);
+  const bool fits = img.tasks.size() * sizeof(DevTask) <= L.order - L.tasks &&
+                    img.order.size() * sizeof(uint2) <= L.succ - L.order && img.succ.size() * 4 <= L.extra - L.succ &&
+                    img.extra.size() * 8 <= L.comm_n - L.extra && img.comm_n.size() * 4 <= L.cnt - L.comm_n &&
+                    img.cnt.size() * 4 <= L.end - L.cnt;
+  if (!fits) return fail(HICCL_ERR_HIP, "static scratch layout does not match the task table");
+  s.blob.assign(L.end - L.tasks, 0);
+  auto put = [&](uint64_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(s.blob.data() + (off - L.tasks), src, bytes);
+  };
+  put(L.tasks, img.tasks.data(), img.tasks.size() * sizeof(DevTask));
+  put(L.order, img.order.data(), img.order.size() * sizeof(uint2));
+  put(L.succ, img.succ.data(), img.succ.size() * 4);
+  put(L.extra, img.extra.data(), img.extra.size() * 8);
+  put(L.comm_n, img.comm_n.data(), img.comm_n.size() * 4);
+  put(L.cnt, img.cnt.data(), img.cnt.size() * 4);
+  s.table_off = L.tasks;
+  s.base = base;
+  return 0;
+}
+
+static int static_wait(Comm& c) {
+  if (!c.stat || !c.stat->launched) return HICCL_SUCCESS;
+  HIP_TRY(hipStreamSynchronize(c.stat->stream));
+  int status = 0;
+  if (int rc = read_status(c.stat->ex, &status)) return rc;
+  if (status) return fail(HICCL_ERR_TIMEOUT, "executor gave up a dependency wait (spin limit reached)");
+  return HICCL_SUCCESS;
+}
+
+}  // namespace hiccl
+
+extern "C" {
+
+int hiccl_run_static(hiccl_comm_t comm, void* stream) {
+  if (!comm) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator");
+  Comm& c = comm->c;
+  if (!c.planned) return fail(HICCL_ERR_STATE, "call hiccl_init before hiccl_run_static");
+  const StaticLayout L = static_layout(c.plan);
+  if (L.end > HICCL_STATIC_SCRATCH_BYTES)
+    return fail(HICCL_ERR_INVALID_ARG, "the plan needs " + std::to_string(L.end) +
+                                           " bytes of static scratch (workspace and tables); the limit is " +
+                                           std::to_string(HICCL_STATIC_SCRATCH_BYTES));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (c.dev && c.dev->launched && c.dev->last_stream != st && hipEventQuery(c.dev->ev) == hipErrorNotReady)
+    return fail(HICCL_ERR_STATE, "a run of this communicator is in flight on another stream");
+  if (c.dev && c.dev->ring_id && ring_request_pending(c.dev->ring_id, c.dev->ring_pos))
+    return fail(HICCL_ERR_STATE, "this communicator has a request in a device ring");
+  if (c.dev && c.dev->batch && batch_in_flight_elsewhere(c.dev->batch, st))
+    return fail(HICCL_ERR_STATE, "a batch run holding this communicator is in flight on another stream");
+  if (c.stat && c.stat->launched && c.stat->stream != st && hipStreamQuery(c.stat->stream) == hipErrorNotReady)
+    return fail(HICCL_ERR_STATE, "a static run of this communicator is in flight on another stream");
+  void* base = nullptr;
+  if (int rc = static_scratch(&base)) return rc;
+  if (!c.stat || c.stat->base != base) {
+    auto* s = new StaticState;
+    if (int rc = static_build(c, L, base, *s)) {
+      delete s;
+      return rc;
+    }
+    static_state_free(c.stat);
+    c.stat = s;
+  }
+  StaticState& s = *c.stat;
+  Exe& ex = s.ex;
+  ex.spin_limit = c.exec.spin_limit;
+  ex.grid = std::min<int>(device_grid(c.exec.grid), std::max<uint32_t>(1u, ex.ntiles));
+  ex.stage_grid = c.exec.grid;
+  ex.queues = uint32_t(std::max(1, std::min<int>(c.exec.queues, std::min<int>(kMaxQueues, ex.grid))));
+  // the table and fresh counters, then the kernels: everything on `stream`, in order
+  HIP_TRY(hipMemcpyAsync(static_cast<unsigned char*>(base) + s.table_off, s.blob.data(), s.blob.size(),
+                         hipMemcpyHostToDevice, st));
+  if (int rc = launch(ex, st)) return rc;
+  s.stream = st;
+  s.launched = true;
+  c.last_static = true;
   return HICCL_SUCCESS;
 }
 
@@ -1868,7 +2084,10 @@ int hiccl_run_batch(const hiccl_comm_t* comms, int n, void* stream, int mode) {
     g_batches.push_back({std::vector<hiccl_comm_t>(comms, comms + n), mode, b});
   }
   if (int rc = hiccl_batch_run(b, stream)) return rc;
-  for (int m = 0; m < n; ++m) comms[m]->c.dev->batch = b;
+  for (int m = 0; m < n; ++m) {
+    comms[m]->c.dev->batch = b;
+    comms[m]->c.last_static = false;
+  }
   return HICCL_SUCCESS;
 }
 

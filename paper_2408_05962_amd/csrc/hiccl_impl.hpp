@@ -119,6 +119,8 @@ struct ExecCfg {
 struct DeviceState;              // device.hip
 void device_state_free(DeviceState*);
 void device_state_set_spin_limit(DeviceState*, uint32_t polls);   // takes effect on the next run
+struct StaticState;              // device.hip: host image of the tables for hiccl_run_static
+void static_state_free(StaticState*);
 
 struct Comm {
   int P = 1;
@@ -134,7 +136,12 @@ struct Comm {
   void* user_ws = nullptr;
   size_t user_ws_bytes = 0;
   DeviceState* dev = nullptr;
-  ~Comm() { if (dev) device_state_free(dev); }
+  StaticState* stat = nullptr;
+  bool last_static = false;      // the latest run was hiccl_run_static (hiccl_wait follows it)
+  ~Comm() {
+    if (dev) device_state_free(dev);
+    if (stat) static_state_free(stat);
+  }
 };
 
 // ------------------------------------------------------------ error helpers

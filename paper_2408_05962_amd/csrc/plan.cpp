@@ -1190,6 +1190,14 @@ int hiccl_add_fence(hiccl_comm_t comm) {
   return HICCL_SUCCESS;
 }
 
+static void drop_static(Comm& c) {
+  if (c.stat) {
+    static_state_free(c.stat);
+    c.stat = nullptr;
+  }
+  c.last_static = false;
+}
+
 static void unplan(Comm& c) {
   c.planned = false;
   c.plan = Plan();
@@ -1197,6 +1205,7 @@ static void unplan(Comm& c) {
     device_state_free(c.dev);
     c.dev = nullptr;
   }
+  drop_static(c);
 }
 
 int hiccl_set_hierarchy(hiccl_comm_t comm, const int* factors, int nlevels) {
@@ -1271,6 +1280,7 @@ int hiccl_set_claim(hiccl_comm_t comm, int queues, int batch) {
     device_state_free(comm->c.dev);
     comm->c.dev = nullptr;
   }
+  drop_static(comm->c);
   return HICCL_SUCCESS;
 }
 

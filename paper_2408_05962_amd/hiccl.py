@@ -84,6 +84,7 @@ def lib():
             "hiccl_workspace_size": [vp, C.POINTER(sz)],
             "hiccl_set_workspace": [vp, vp, sz],
             "hiccl_run": [vp, vp],
+            "hiccl_run_static": [vp, vp],
             "hiccl_wait": [vp],
             "hiccl_query_bytes": [vp, pi, i, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)],
             "hiccl_plan_info": [vp, C.POINTER(PlanInfo)],
@@ -246,6 +247,11 @@ class Comm:
     # execution ------------------------------------------------------------------
     def run(self, stream=None):
         return check(lib().hiccl_run(self.h, stream_handle(stream)))
+
+    def run_static(self, stream=None):
+        """hiccl_run without any device allocation: tables, counters and workspace in the library's static
+        device scratch (calls that overlap on one GPU race)."""
+        return check(lib().hiccl_run_static(self.h, stream_handle(stream)))
 
     def wait(self):
         return check(lib().hiccl_wait(self.h))

@@ -430,3 +430,25 @@ def test_run_batch_and_submit_argument_errors(hc):
     t = C.c_uint64()
     assert lib.hiccl_server_submit(None, c.h, C.byref(t)) == hc.ERR_INVALID_ARG
     c.close()
+
+
+def test_run_static_checks_before_any_device_call(hc):
+    """hiccl_run_static (the allocation-free entry point): NULL and uninitialized communicators are
+    refused, and a plan whose workspace and tables exceed the static scratch is refused with
+    INVALID_ARG before anything touches a device (this runs on a host without one)."""
+    import ctypes as C
+    lib = hc.lib()
+    assert lib.hiccl_run_static(None, None) == hc.ERR_INVALID_ARG
+    p, d = 16, 1 << 20
+    s, r = _bufs(p, d * p), _bufs(p, d * p)
+    c = hc.Comm(p, "float32")
+    from paper_2408_05962_amd import collectives as CO
+    CO.compose(c, "all_reduce", s, r, d)
+    c.set_hierarchy([2, 4, 2])
+    c.set_stripe(4)
+    assert lib.hiccl_run_static(c.h, None) == hc.ERR_STATE
+    c.init()
+    assert c.workspace_size() > (64 << 20)        # 16 ranks x 4 MiB chunks: workspace alone exceeds 64 MiB
+    assert lib.hiccl_run_static(c.h, None) == hc.ERR_INVALID_ARG
+    assert b"static scratch" in lib.hiccl_last_error()
+    c.close()

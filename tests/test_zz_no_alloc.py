@@ -1,0 +1,121 @@
+"""The allocation-free entry point hiccl_run_static against hiccl_run, through the C ABI: the same
+communicator setup run both ways gives the same bytes. Consecutive static calls reuse one static
+scratch per GPU; each call re-copies its tables and counters, so a smaller plan after a larger one
+(and the larger one again after it) still runs correctly."""
+import numpy as np
+import pytest
+
+from tests.conftest import gpu_available
+from tests import harness as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not gpu_available():
+        pytest.skip("no GPU")
+    from paper_2408_05962_amd import hiccl
+    hiccl.lib()
+    return torch
+
+
+CASES = [
+    # name, p, hierarchy, dtype, d, stripe, pipeline, executor
+    ("all_reduce", 16, [2, 4, 2], "float32", 50003, 4, 2, "persistent"),
+    ("reduce_scatter", 8, [2, 4], "int32", 3001, 2, 2, "staged"),
+    ("all_reduce", 8, [8], "fp8_e4m3", 1024, 1, 2, "persistent"),     # 8-operand nodes: operand arrays
+    ("all_to_all", 4, [2, 2], "float32", 257, 1, 1, "staged"),
+]
+
+
+def _make(torch, case, seed):
+    """Device buffers and two identical communicators over them (one per entry point)."""
+    import synth
+    from paper_2408_05962_amd import collectives as CO
+    from paper_2408_05962_amd import to_payload
+    name, p, h, dtype, d, s, m, mode = case
+    n = H.send_len(name, p, d)
+    rl = H.recv_len(name, p, d)
+    if dtype == "fp8_e4m3":
+        X = synth.device_buffers("float32_outliers", seed, p, n)
+        Y = torch.empty((p, n), dtype=torch.uint8, device="cuda")
+        Sc = torch.empty((p, n // 256), dtype=torch.float32, device="cuda")
+        for r in range(p):
+            to_payload("fp8_e4m3", X[r], Y[r], Sc[r], n)
+        R = torch.zeros((p, rl), dtype=torch.uint8, device="cuda")
+        RS = torch.zeros((p, rl // 256), dtype=torch.float32, device="cuda")
+        send = [(Y[r], Sc[r]) for r in range(p)]
+        recv = [(R[r], RS[r]) for r in range(p)]
+        keep = (X, Y, Sc)
+    else:
+        X = synth.device_buffers("int32" if dtype == "int32" else "float32", seed, p, n)
+        R = torch.zeros((p, rl), dtype=X.dtype, device="cuda")
+        RS = None
+        send = [X[r] for r in range(p)]
+        recv = [R[r] for r in range(p)]
+        keep = (X,)
+    comms = []
+    for _ in range(2):
+        c = CO.make(name, p, dtype, send, recv, d, hierarchy=h, stripe=s, pipeline=m, exec_mode=mode)
+        c.set_spin_limit(1 << 20)
+        comms.append(c)
+    return comms, R, RS, keep
+
+
+def _result(torch, R, RS):
+    torch.cuda.synchronize()
+    out = R.cpu().numpy().copy()
+    return out, (RS.cpu().numpy().copy() if RS is not None else None)
+
+
+def test_static_matches_run_on_consecutive_calls(torch_cuda):
+    torch = torch_cuda
+    st = torch.cuda.current_stream()
+    made = [_make(torch, case, 500 + i) for i, case in enumerate(CASES)]
+    expect = []
+    for comms, R, RS, _ in made:
+        R.zero_()
+        if RS is not None:
+            RS.zero_()
+        comms[1].run(st)                   # the existing entry point
+        comms[1].wait()
+        expect.append(_result(torch, R, RS))
+    # static calls in a row, each plan smaller than the one before, then the first again (its tables
+    # were overwritten by the others in the shared scratch)
+    for k in list(range(len(CASES))) + [0, 2]:
+        comms, R, RS, _ = made[k]
+        print(f"[static] case {k}: {CASES[k]}", flush=True)
+        R.fill_(7)
+        if RS is not None:
+            RS.fill_(7)
+        comms[0].run_static(st)
+        comms[0].wait()
+        got, gs = _result(torch, R, RS)
+        er, es = expect[k]
+        assert np.array_equal(got, er), f"case {k}: static run differs from hiccl_run"
+        if es is not None:
+            assert np.array_equal(gs, es), f"case {k}: static run's block scales differ"
+    for comms, _, _, _ in made:
+        for c in comms:
+            c.close()
+
+
+def test_static_after_run_and_run_after_static(torch_cuda):
+    """One communicator alternating between the two entry points on one stream."""
+    torch = torch_cuda
+    st = torch.cuda.current_stream()
+    comms, R, RS, _ = _make(torch, CASES[0], 77)
+    c = comms[0]
+    ref = None
+    for k, how in enumerate(["run", "static", "static", "run", "static"]):
+        R.fill_(-1)
+        (c.run if how == "run" else c.run_static)(st)
+        c.wait()
+        got, _ = _result(torch, R, RS)
+        if ref is None:
+            ref = got
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), f"call {k} ({how}) differs"
+    for x in comms:
+        x.close()
