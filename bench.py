@@ -486,11 +486,13 @@ def _errors(got, exact, scale):
 
 
 # ----------------------------------------------------------------- precision
-def precision_bench(torch, reps=5, n=1 << 28, sample_blocks=64):
+def precision_bench(torch, reps=3, n=1 << 28):
     """All-Reduce and Reduce-Scatter over 16 ranks as {2,4,2}, 2^28 elements per rank ~ N(0,1) with 1 % of
     entries x 1e3, stripe 4, pipeline 8; payload float32 vs bf16 vs fp8-e4m3 (per-256 power-of-two
-    scales), float32 accumulation. Error vs the float64 sum of the original float32 inputs on sampled
-    256-element blocks of every rank's chunk."""
+    scales), float32 accumulation. Both executors run every result (one warm run, then `reps` timed) and
+    must leave the same bytes; the error of that result against the float64 sum of the original float32
+    inputs is measured over the whole chunks 0 and p-1 (every stripe, channel and tile boundary of a
+    chunk)."""
     import numpy as np
 
     import synth
@@ -500,33 +502,36 @@ def precision_bench(torch, reps=5, n=1 << 28, sample_blocks=64):
     d = n // p
     X = synth.device_buffers("float32_outliers", 301, p, n)
     st = torch.cuda.current_stream()
-    rng = np.random.default_rng(1)
-    out = {"ranks": p, "elements_per_rank": n, "stripe": s, "pipeline": m, "results": []}
+    chunks = (0, p - 1)
+    # the exact sums of the scored chunks, from the original float32 inputs
+    exact = {}
+    for j in chunks:
+        xs = X[:, j * d:(j + 1) * d].cpu().numpy().astype(np.float64)
+        exact[j] = (xs.sum(0), np.abs(xs).sum(0))
+        del xs
+    out = {"ranks": p, "elements_per_rank": n, "stripe": s, "pipeline": m, "timed_reps": reps,
+           "scored": f"whole chunks {list(chunks)} ({d} elements each) of every result, against the float64 "
+                    "sum of the original float32 inputs", "results": []}
+    W = torch.empty(d, dtype=torch.float32, device="cuda")
     for name in ("all_reduce", "reduce_scatter"):
         rl = recv_len(name, p, d)
         for dtype in ("float32", "bfloat16", "fp8_e4m3"):
+            es = {"float32": 4, "bfloat16": 2, "fp8_e4m3": 1}[dtype]
+            tdt = {"float32": torch.float32, "bfloat16": torch.int16, "fp8_e4m3": torch.uint8}[dtype]
+            Y = Sc = None
             if dtype == "float32":
                 send = [X[r] for r in range(p)]
-                R = torch.zeros((p, rl), dtype=torch.float32, device="cuda")
-                recv = [R[r] for r in range(p)]
-                Y = Sc = RS = None
-            elif dtype == "bfloat16":
-                Y = torch.empty((p, n), dtype=torch.int16, device="cuda")
-                for r in range(p):
-                    to_payload("bfloat16", X[r], Y[r], None, n, st)
-                R = torch.zeros((p, rl), dtype=torch.int16, device="cuda")
-                send, recv, Sc, RS = [Y[r] for r in range(p)], [R[r] for r in range(p)], None, None
             else:
-                Y = torch.empty((p, n), dtype=torch.uint8, device="cuda")
-                Sc = torch.empty((p, n // 256), dtype=torch.float32, device="cuda")
+                Y = torch.empty((p, n), dtype=tdt, device="cuda")
+                Sc = torch.empty((p, n // 256), dtype=torch.float32, device="cuda") if dtype == "fp8_e4m3" else None
                 for r in range(p):
-                    to_payload("fp8_e4m3", X[r], Y[r], Sc[r], n, st)
-                R = torch.zeros((p, rl), dtype=torch.uint8, device="cuda")
-                RS = torch.zeros((p, rl // 256), dtype=torch.float32, device="cuda")
-                send = [(Y[r], Sc[r]) for r in range(p)]
-                recv = [(R[r], RS[r]) for r in range(p)]
-            times = {}
+                    to_payload(dtype, X[r], Y[r], Sc[r] if Sc is not None else None, n, st)
+                send = [Y[r] for r in range(p)] if Sc is None else [(Y[r], Sc[r]) for r in range(p)]
+            times, res, info = {}, {}, None
             for mode in ("staged", "persistent"):
+                R = torch.zeros((p, rl), dtype=tdt, device="cuda")
+                RS = torch.zeros((p, rl // 256), dtype=torch.float32, device="cuda") if dtype == "fp8_e4m3" else None
+                recv = [R[r] for r in range(p)] if RS is None else [(R[r], RS[r]) for r in range(p)]
                 c = CO.make(name, p, dtype, send, recv, d, hierarchy=h, stripe=s, pipeline=m, exec_mode=mode)
                 info = c.plan_info()
                 c.run(st)
@@ -540,40 +545,40 @@ def precision_bench(torch, reps=5, n=1 << 28, sample_blocks=64):
                 torch.cuda.synchronize()
                 times[mode] = e0.elapsed_time(e1) / reps
                 c.close()
-            ms = times["staged"]
-            # errors on sampled blocks: the library widens the result rows to float32 on the device;
-            # the exact value is the float64 sum of the original float32 inputs
+                res[mode] = (R, RS)
+            (R, RS), (R2, RS2) = res["staged"], res["persistent"]
+            same = bool(torch.equal(R, R2) and (RS is None or torch.equal(RS, RS2)))
+            assert same, f"precision {name} {dtype}: the two executors' results differ"
+            del res, R2, RS2
+            # error over the scored chunks: the library widens the result to float32 on the device
             errs = []
-            W = torch.empty(rl, dtype=torch.float32, device="cuda")
-            for j in rng.integers(0, p, 4):
-                j = int(j)
+            for j in chunks:
+                col = 0 if name == "reduce_scatter" else j * d
                 if dtype == "float32":
-                    W.copy_(R[j])
-                elif dtype == "bfloat16":
-                    from_payload("bfloat16", R[j], None, W, rl, st)
+                    W.copy_(R[j, col:col + d])
                 else:
-                    from_payload("fp8_e4m3", R[j], RS[j], W, rl, st)
+                    from_payload(dtype, R[j, col:col + d], RS[j, col // 256:(col + d) // 256] if RS is not None else None,
+                                 W, d, st)
                 torch.cuda.synchronize()
-                blocks = rng.integers(0, d // 256, sample_blocks // 4)
-                for b in blocks:
-                    lo = j * d + int(b) * 256
-                    col = int(b) * 256 if name == "reduce_scatter" else lo
-                    xs = X[:, lo:lo + 256].cpu().numpy().astype(np.float64)
-                    errs.append(_errors(W[col:col + 256].cpu().numpy().astype(np.float64), xs.sum(0),
-                                        np.abs(xs).sum(0)))
-            del W
+                errs.append(_errors(W.cpu().numpy().astype(np.float64), *exact[j]))
             worst = {k: max(e[k] for e in errs) for k in errs[0]}
             exec_b = info["hbm_read"] + info["hbm_written"]
-            _progress(f"precision {name} {dtype}: staged {ms:.3f} ms, persistent {times['persistent']:.3f} ms")
-            out["results"].append({"collective": name, "payload": dtype, "ms": round(ms, 3),
-                                   "ms_persistent": round(times["persistent"], 3),
-                                   "algbw_GBps": round(n * 4 / ms / 1e6, 1),
-                                   "exec_bytes": exec_b, "exec_GBps": round(exec_b / ms / 1e6, 1),
-                                   "hbm_frac": round(exec_b / ms / 1e6 / PEAK_HBM, 4),
-                                   "error_vs_float64": {k: float(f"{v:.3e}") for k, v in worst.items()}})
-            del R, Y, Sc, RS, send, recv
+            ms = times["staged"]
+            _progress(f"precision {name} {dtype}: staged {ms:.3f} ms, persistent {times['persistent']:.3f} ms, "
+                      f"scaled error {worst['scaled']:.3e}")
+            out["results"].append({
+                "collective": name, "payload": dtype, "ms": round(ms, 3),
+                "ms_persistent": round(times["persistent"], 3),
+                "algbw_GBps": round(n * es / ms / 1e6, 1),
+                "algbw_float32_equivalent_GBps": round(n * 4 / ms / 1e6, 1),
+                "exec_bytes": exec_b, "exec_GBps": round(exec_b / ms / 1e6, 1),
+                "hbm_frac": round(exec_b / ms / 1e6 / PEAK_HBM, 4),
+                "hbm_frac_persistent": round(exec_b / times["persistent"] / 1e6 / PEAK_HBM, 4),
+                "executors_bit_identical": same,
+                "error_vs_float64": {k: float(f"{v:.3e}") for k, v in worst.items()}})
+            del R, RS, Y, Sc, send
             torch.cuda.empty_cache()
-    del X
+    del X, W
     torch.cuda.empty_cache()
     return out
 
@@ -698,6 +703,46 @@ def serve_bench(torch, ntemplates=48, nreq=2000, fractions=(0.25, 0.5, 0.75, 0.9
     return out
 
 
+def empirical_bound(torch, nbytes=1 << 30, reps=10):
+    """Empirical device-memory bound in the same run (the analog of the paper's empirical bounds): one
+    1 GiB copy as the executor's own plan (a one-leaf multicast between two virtual ranks, one copy task
+    of 32768 tiles), on each executor, and hipMemcpyAsync device-to-device. Read + write bytes over the
+    event-timed duration."""
+    import ctypes
+
+    from paper_2408_05962_amd import Comm
+    n = nbytes // 4
+    x = torch.empty(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    st = torch.cuda.current_stream()
+    out = {"bytes_per_copy": nbytes}
+    for mode in ("staged", "persistent"):
+        c = Comm(2, "float32")
+        c.add_multicast([x, x], [y, y], n, 0, [1])
+        c.set_hierarchy([2])
+        c.set_exec(mode)
+        c.init()
+        out[f"hiccl_copy_{mode}_GBps"] = round(2 * nbytes / _time_comm(torch, c, reps=reps) / 1e6, 1)
+        c.close()
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                   ctypes.c_void_p]
+    hip.hipMemcpyAsync.restype = ctypes.c_int
+    D2D = 3        # hipMemcpyDeviceToDevice
+    for _ in range(3):
+        assert hip.hipMemcpyAsync(y.data_ptr(), x.data_ptr(), nbytes, D2D, st.cuda_stream) == 0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        assert hip.hipMemcpyAsync(y.data_ptr(), x.data_ptr(), nbytes, D2D, st.cuda_stream) == 0
+    e1.record(st)
+    torch.cuda.synchronize()
+    out["hipMemcpyDtoD_GBps"] = round(2 * nbytes / (e0.elapsed_time(e1) / reps) / 1e6, 1)
+    del x, y
+    return out
+
+
 def measured_traffic(mode, tile, grid):
     """HBM bytes per launch of the headline kernel from the committed rocprofv3 counter runs
     (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None when they were taken on other kernel
@@ -730,10 +775,13 @@ def main():
     ap.add_argument("--batch", action="store_true", help="(default) measure the batching form: 512 collectives, "
                     "batched vs one launch per collective, throughput and p50/p99 latency")
     ap.add_argument("--no-batch", action="store_true", help="skip the batching form")
-    ap.add_argument("--serve", action="store_true", help="also measure the serving form (Poisson requests)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving form (Poisson requests)")
+    ap.add_argument("--serve-requests", type=int, default=500, help="requests per arrival rate")
+    ap.add_argument("--serve-rates", default="0.5,0.9,1.2",
+                    help="arrival rates as fractions of the closed-loop service rate")
     ap.add_argument("--serve-exec", default="persistent", choices=["staged", "persistent"],
                     help="executor of the serving templates")
-    ap.add_argument("--precision", action="store_true", help="also measure the precision form (bf16 / fp8)")
+    ap.add_argument("--no-precision", action="store_true", help="skip the precision form (bf16 / fp8)")
     ap.add_argument("--sweep", action="store_true",
                     help="also measure pipeline depth, ring vs tree, two-step compositions, the autotuners, "
                          "Scatter / Gather, one rank's share and the small All-Reduce")
@@ -821,19 +869,7 @@ def main():
     assert torch.all(got == got[0]), "All-Reduce rows differ"
     assert torch.allclose(got[0], ref, rtol=1e-5, atol=1e-4), "All-Reduce disagrees with the sampled sum"
 
-    # empirical copy bound in the same run: a 1 GiB device-to-device copy
-    x = torch.empty(2 ** 28, dtype=torch.float32, device=dev)
-    y = torch.empty_like(x)
-    for _ in range(3):
-        y.copy_(x)
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    c0.record(st)
-    for _ in range(10):
-        y.copy_(x)
-    c1.record(st)
-    torch.cuda.synchronize()
-    copy_gbps = 2 * x.numel() * 4 / (c0.elapsed_time(c1) / 10) / 1e6
-    del x, y
+    bound = empirical_bound(torch)
 
     achieved = kern_bytes / kern_ms / 1e6
     kname = "hiccl_staged<256, false>" if args.mode == "staged" else "hiccl_persistent<256, false>"
@@ -856,12 +892,15 @@ def main():
                                "stripe 4, pipeline 8",
                    "executor": args.mode, "tile_bytes": head["tile"] or "default", "grid": head["grid"] or "default"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM, 4), "traffic": traffic, "kernel": kname,
-                     "launches_per_step": head["launches"],
+                     "frac": round(achieved / PEAK_HBM, 4), "traffic": traffic,
+                     # counted HBM bytes (calibrated FETCH_SIZE + WRITE_SIZE per launch) over the launch time
+                     "hbm_counted_frac": (round(traffic / (kern_ms * 1e-3 / head["launches"]) / 1e9 / PEAK_HBM, 4)
+                                          if traffic else None),
+                     "kernel": kname, "launches_per_step": head["launches"],
                      "bytes_per_launch": round(kern_bytes / head["launches"]),
                      "avg_launch_us": round(kern_ms * 1e3 / head["launches"], 2)},
         "per_collective": per,
-        "empirical_copy_GBps": round(copy_gbps, 1),
+        "empirical_bound": bound,
     }
     if alt is not None:
         out["other_executor"] = {"executor": alt_mode, "ms_per_step": round(alt["step_ms"], 4),
@@ -871,7 +910,7 @@ def main():
                                  "per_collective_ms": {n: v["ms"] for n, v in alt["per"].items()}}
     del bufs
     torch.cuda.empty_cache()
-    if args.precision:
+    if not args.no_precision:
         out["precision"] = precision_bench(torch)
         torch.cuda.empty_cache()
     if args.sweep:
@@ -880,8 +919,9 @@ def main():
     if not args.no_batch:
         out["batching"] = batch_bench(torch)
         torch.cuda.empty_cache()
-    if args.serve:
-        out["serving"] = serve_bench(torch, mode=args.serve_exec)
+    if not args.no_serve:
+        rates = tuple(float(x) for x in args.serve_rates.split(","))
+        out["serving"] = serve_bench(torch, nreq=args.serve_requests, fractions=rates, mode=args.serve_exec)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
