@@ -122,23 +122,21 @@ __device__ __forceinline__ int scale_exp(float amax) {
 constexpr int kUnroll = 8;     // 16-byte vectors in flight per lane and operand
 
 // Data path. Every operand byte is read and written with buffer
-// instructions that carry the streaming (nt) and device-coherent (sc1)
-// cache policy: a tile's stores are visible to any workgroup on any XCD as
-// soon as they complete, and a dependent tile's loads never hit a stale
-// line in a per-XCD L2 or per-CU L1. Retiring a tile then needs only
-// "stores complete" (s_waitcnt) and a counter increment, with no L2-wide
-// writeback or invalidate. The buffer range of each operand is exactly the
-// tile, so the hardware bounds check drops any access outside it.
-//
-// Stage launches store without the streaming hint (sc1 only). Their
-// consumers run in a later launch, and the end of a launch writes the
-// L2 back, so visibility holds there too. The stores then stay in the
-// caches, where the next stage finds the last of them (its tiles run in
-// the opposite order, see upload).
+// instructions whose scope is the device (sc1): a tile's stores are visible
+// to any workgroup on any XCD as soon as they complete, and a dependent
+// tile's loads never hit a stale line in a per-XCD L2 or per-CU L1.
+// Retiring a tile then needs only "stores complete" (s_waitcnt) and a
+// counter increment, with no L2-wide writeback or invalidate. Loads and the
+// stores of final results (tasks without successors) also carry the
+// streaming hint (nt); stores that a later task reads do not, so their lines
+// stay in the caches for that consumer (run_tile_by_use). The buffer range
+// of each operand is exactly the tile, so the hardware bounds check drops
+// any access outside it. Stage launches run every other stage's tiles in
+// reverse (see upload), so a stage first reads what its producer wrote last.
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
 constexpr int kPolicy = 2 | 16;               // nt | sc1
-constexpr int kStagePolicy = 16;              // sc1: stores of stage launches
+constexpr int kStagePolicy = 16;              // sc1: stores that a later task reads
 constexpr int kRsrcWord3 = 0x00020000;        // raw (untyped) buffer, gfx9 family
 
 __device__ __forceinline__ rsrc_t rsrc(uint64_t base, uint64_t bytes) {
@@ -638,6 +636,20 @@ __device__ __forceinline__ void run_tile(const DevTask* __restrict__ t, uint32_t
   }
 }
 
+// Store policy by consumer: a tile whose task has successors writes its lines
+// with device scope only (sc1), so they stay in the caches for the consumer
+// tasks that read them next; a task without successors writes a final result
+// that nothing in this run reads, and streams it (nt sc1). Both are
+// device-coherent, so the choice changes where lines are kept, never what a
+// consumer on another XCD reads.
+template <int BLOCK, bool NARROW>
+__device__ __forceinline__ void run_tile_by_use(const DevTask* __restrict__ t, uint32_t q) {
+  if (uni32(t->nsucc))
+    run_tile<BLOCK, NARROW, kStagePolicy>(t, q);
+  else
+    run_tile<BLOCK, NARROW, kPolicy>(t, q);
+}
+
 __device__ __forceinline__ unsigned long long dev_clock() { return wall_clock64(); }
 
 // Retire-side fields of a claimed tile's task, read from the task's
@@ -835,7 +847,7 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
       }
     } else if (ready) {
       const DevTask* t = &s_task[cur];
-      run_tile<BLOCK, NARROW>(t, __builtin_amdgcn_readfirstlane(s_q[cur]));
+      run_tile_by_use<BLOCK, NARROW>(t, __builtin_amdgcn_readfirstlane(s_q[cur]));
       // a tile whose retire releases something (successors, a completion
       // stamp) has its stores complete before the barrier; any other tile's
       // stores drain while the next tile streams, and the kernel's end
@@ -892,7 +904,7 @@ __global__ __launch_bounds__(BLOCK) void hiccl_staged(ExecArgs a, uint32_t lo, u
   for (uint32_t tl = lo + blockIdx.x; tl < hi; tl += gridDim.x) {
     const uint2 o = a.order[tl];
     const uint32_t k = __builtin_amdgcn_readfirstlane(o.x);
-    run_tile<BLOCK, NARROW, kStagePolicy>(a.tasks + k, __builtin_amdgcn_readfirstlane(o.y));
+    run_tile_by_use<BLOCK, NARROW>(a.tasks + k, __builtin_amdgcn_readfirstlane(o.y));
   }
 }
 
@@ -1045,7 +1057,7 @@ __global__ __launch_bounds__(BLOCK) void hiccl_ring(RingArgs r) {
       __syncthreads();
       const uint32_t tl = __builtin_amdgcn_readfirstlane(s_word[1]);
       if (tl == kNoTile) break;
-      run_tile<BLOCK, true>(&s_task, __builtin_amdgcn_readfirstlane(s_word[2]));
+      run_tile_by_use<BLOCK, true>(&s_task, __builtin_amdgcn_readfirstlane(s_word[2]));
       wait_mem();
       __syncthreads();
       if (lead) retire(a, ref_of(s_task, s_word[0]));

@@ -6,6 +6,8 @@ four counter runs (FETCH_SIZE, then WRITE_SIZE, for each executor). Writes
   profiles/hiccl_<executor>_six_collectives_16r_64MiB.md        stats, trace-timed dispatches, traffic
   profiles/hiccl_staged_per_stage_six_collectives_16r_64MiB.md  every stage launch of one pass
   profiles/traffic_hiccl_<executor>_six_collectives_16r_64MiB.json  what bench.py reports as `traffic`
+  profiles/precision_kernels_allreduce_reducescatter_16r_2e28.md  (with --precision-trace) the kernels of
+                                                                  the precision form and its results
 
 Counted bytes: FETCH_SIZE and WRITE_SIZE are read per dispatch in KiB and scaled by what the same counter
 reads for a copy of known size in the same process (the 1 GiB device-to-device hipMemcpyAsync that
@@ -123,7 +125,7 @@ def _stats_table(trace_dir):
     rows = _csv(trace_dir, "kernel_stats.csv")
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     lines = ["| kernel | calls | avg ns | total ns | % |", "|---|---|---|---|---|"]
-    for r in rows[:8]:
+    for r in rows[:12]:
         lines.append(f"| {r['Name'][:60]} | {r['Calls']} | {float(r['AverageNs']):.0f} | {r['TotalDurationNs']} | "
                      f"{float(r['Percentage']):.2f} |")
     return "\n".join(lines)
@@ -144,8 +146,12 @@ def main():
     for mode in ("staged", "persistent"):
         ap.add_argument(f"--fetch-{mode}", required=True)
         ap.add_argument(f"--write-{mode}", required=True)
+    ap.add_argument("--precision-trace", help="kernel-trace run of the precision form (optional)")
+    ap.add_argument("--precision-log", help="captured output of that run (bench.py's JSON line)")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     args = ap.parse_args()
+    if args.precision_trace:
+        _precision(args)
     P = plans()
     src, isa = _digests()
     line = _bench_line(args.trace_log)
@@ -207,6 +213,42 @@ Commands (from the repository root on one MI355X), then this summary:
         if mode == "staged":
             _per_stage(args, P, disp, launches, w, k, isa)
     print(f"wrote summaries to {args.out}")
+
+
+PRECISION_ARGS = "--steps 1 --warmup 0 --no-batch --no-alt --no-cpu-baseline --no-serve"
+
+
+def _precision(args):
+    """Kernel stats of a run that includes the precision form, and that run's precision results."""
+    line = _bench_line(args.precision_log)
+    rows = []
+    for r in (line or {}).get("precision", {}).get("results", []):
+        rows.append(f"| {r['collective']} | {r['payload']} | {r['ms']} | {r['ms_persistent']} | {r['exec_GBps']} | "
+                    f"{r['hbm_frac']} | {r['hbm_frac_persistent']} | {r['error_vs_float64']['scaled']:.3e} |")
+    _, isa = _digests()
+    md = f"""# Precision form kernels: All-Reduce and Reduce-Scatter, 16 ranks as {{2,4,2}}, 2^28 elements per rank, stripe 4, pipeline 8, float32 / bf16 / fp8-e4m3
+
+Command (from the repository root on one MI355X), then this summary:
+
+    rocprofv3 --kernel-trace --stats --output-format csv -d {args.precision_trace} -o prec -- python3 bench.py {PRECISION_ARGS}
+    python rocprof_summary.py ... --precision-trace {args.precision_trace} --precision-log <captured output>
+
+`<256, true>` kernels are built with the bf16 / fp8 tile paths; `<256, false>` serve int32 / float32 (here: the float32 payload runs and one headline pass). `k_to_bf16` / `k_to_fp8` convert the float32 inputs to the payload format and `k_from_*` widen results for scoring, outside the timed runs.
+
+## Kernel stats (rocprofv3 --stats)
+
+{_stats_table(args.precision_trace)}
+
+## The same run's bench.py precision results (HIP events, one warm and 3 timed runs per executor)
+
+| collective | payload | staged ms | persistent ms | executed GB/s (staged) | fraction of 8 TB/s (staged) | (persistent) | scaled error vs float64 |
+|---|---|---|---|---|---|---|---|
+{chr(10).join(rows)}
+
+ kernel instructions sha256 (paper_2408_05962_amd/build.py): {isa}
+"""
+    with open(os.path.join(args.out, "precision_kernels_allreduce_reducescatter_16r_2e28.md"), "w") as f:
+        f.write(md)
 
 
 def _per_stage(args, P, disp, launches, w, k, isa):
