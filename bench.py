@@ -101,64 +101,49 @@ def _mk(torch, CO, name, p, h, dtype, per_rank_bytes, seed, s=1, m=1, tile=0, gr
     return c, snd, rcv, d * p * es
 
 
-def tune_table(torch, seed=9):
-    """Autotuned (stripe, pipeline, tile) per (collective, size class), on buffers of a different seed."""
-    from paper_2408_05962_amd import autotune_model
-    from paper_2408_05962_amd import collectives as CO
-    table = {}
-    st = torch.cuda.current_stream()
-    for name in SIX:
-        for ci, (lo, hi) in enumerate(SIZE_CLASSES):
-            size = int((lo * hi) ** 0.5) // (BATCH_P * 16) * (BATCH_P * 16)
-            c, snd, rcv, _ = _mk(torch, CO, name, BATCH_P, BATCH_H, "float32", size, seed * 100 + ci)
-            r = autotune_model(c, [1, 2, 4], [1, 2, 4, 8], [16384, 65536], reps=3, anchors=5, top=3, stream=st)
-            table[(name, ci)] = (r["stripe"], r["pipeline"], r["tile_bytes"])
-            _progress(f"tuned {name} class {ci}: {table[(name, ci)]}")
-            c.close()
-            del snd, rcv
-    return table
-
-
-def batch_policy(torch, table, n=128, seed=99):
-    """Batch-level tuning: on a batch drawn like the measured one but from another seed, time the merged
-    persistent launch with the per-class table and with the defaults (s = m = 1, default tile), and
-    return the faster policy ("table" or "defaults") with both times."""
+def tune_batch_policy(torch, n=256, seed=99):
+    """Batched-context tuning: on a batch drawn like the measured one but from another seed, the library's
+    batch autotuner (hiccl_autotune_batch) picks (stripe, pipeline, tile) per (collective, size class) by
+    coordinate descent on the merged persistent launch, starting from the defaults (s = m = 1, default
+    tile). Returns the per-class table, the tuning batch's time under the defaults and tuned, and the time
+    spent."""
     import synth
-    from paper_2408_05962_amd import Batch
+    from paper_2408_05962_amd import Batch, autotune_batch
     from paper_2408_05962_amd import collectives as CO
     rng = synth.choice_stream(seed, 2)
     sizes = synth.log_uniform_sizes(seed, n, 4 << 10, 64 << 20, BATCH_P * 16)
     st = torch.cuda.current_stream()
-    bufs, times = [], {}
+    comms, keep, classes = [], [], []
     for i in range(n):
         name = SIX[int(rng.integers(0, 6))]
         dtype = "int32" if rng.random() < 0.5 else "float32"
-        c, snd, rcv, S = _mk(torch, CO, name, BATCH_P, BATCH_H, dtype, sizes[i], 9000 + i)
-        c.close()
-        bufs.append((name, dtype, snd, rcv, S // (BATCH_P * 4), _size_class(sizes[i])))
-    for policy in ("table", "defaults"):
-        comms = []
-        for name, dtype, snd, rcv, d, cls in bufs:
-            s, m, tile = table[(name, cls)] if policy == "table" else (1, 1, 0)
-            comms.append(CO.make(name, BATCH_P, dtype, [snd[r] for r in range(BATCH_P)],
-                                 [rcv[r] for r in range(BATCH_P)], d, hierarchy=BATCH_H, stripe=s, pipeline=m,
-                                 tile_bytes=tile))
-        b = Batch(comms, "persistent")
+        c, snd, rcv, _ = _mk(torch, CO, name, BATCH_P, BATCH_H, dtype, sizes[i], 9000 + i)
+        comms.append(c)
+        keep.append((snd, rcv))
+        classes.append(SIX.index(name) * len(SIZE_CLASSES) + _size_class(sizes[i]))
+    b = Batch(comms, "persistent")
+    b.run(st)
+    b.wait()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(3):
         b.run(st)
-        b.wait()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        for _ in range(3):
-            b.run(st)
-        e1.record(st)
-        b.wait()
-        torch.cuda.synchronize()
-        times[policy] = round(e0.elapsed_time(e1) / 3, 3)
-        b.close()
-        for c in comms:
-            c.close()
-    del bufs
-    return min(times, key=times.get), times
+    e1.record(st)
+    b.wait()
+    torch.cuda.synchronize()
+    default_ms = e0.elapsed_time(e1) / 3
+    b.close()
+    t0 = time.perf_counter()
+    res = autotune_batch(comms, classes, [1, 2, 4], [1, 2, 4, 8], [0, 16384, 131072], mode="persistent", reps=3,
+                         sweeps=2, stream=st)
+    tune_s = time.perf_counter() - t0
+    table = {}
+    for k, choice in enumerate(res["choice"]):
+        table[(SIX[k // len(SIZE_CLASSES)], k % len(SIZE_CLASSES))] = tuple(choice)
+    for c in comms:
+        c.close()
+    del keep
+    return table, {"defaults": round(default_ms, 3), "tuned": round(res["ms"], 3)}, tune_s
 
 
 def batch_bench(torch, n=512, seed=4, reps=3):
@@ -167,11 +152,8 @@ def batch_bench(torch, n=512, seed=4, reps=3):
     import synth
     from paper_2408_05962_amd import Batch
     from paper_2408_05962_amd import collectives as CO
-    t_tune = time.perf_counter()
-    table = tune_table(torch)
-    policy, policy_ms = batch_policy(torch, table)
-    _progress(f"batch policy: {policy} {policy_ms}")
-    t_tune = time.perf_counter() - t_tune
+    table, tuning_ms, tune_s = tune_batch_policy(torch)
+    _progress(f"batch tuning: {tuning_ms} in {tune_s:.1f} s")
     rng = synth.choice_stream(seed, 2)
     sizes = synth.log_uniform_sizes(seed, n, 4 << 10, 64 << 20, BATCH_P * 16)
     items = []
@@ -179,7 +161,7 @@ def batch_bench(torch, n=512, seed=4, reps=3):
     for i in range(n):
         name = SIX[int(rng.integers(0, 6))]
         dtype = "int32" if rng.random() < 0.5 else "float32"
-        s, m, tile = table[(name, _size_class(sizes[i]))] if policy == "table" else (1, 1, 0)
+        s, m, tile = table[(name, _size_class(sizes[i]))]
         c, snd, rcv, S = _mk(torch, CO, name, BATCH_P, BATCH_H, dtype, sizes[i], 5000 + i, s, m, tile)
         info = c.plan_info()
         items.append((c, snd, rcv, S, info["hbm_read"] + info["hbm_written"], name, dtype))
@@ -191,9 +173,12 @@ def batch_bench(torch, n=512, seed=4, reps=3):
     total_exec = sum(it[4] for it in items)
     st = torch.cuda.current_stream()
     out = {"collectives": n, "ranks": BATCH_P, "hierarchy": BATCH_H, "sum_S_bytes": total_S,
-           "sum_exec_bytes": total_exec, "tune_s": round(t_tune, 2), "plan_s": round(t_plan, 2),
+           "sum_exec_bytes": total_exec, "tune_s": round(tune_s, 2), "plan_s": round(t_plan, 2),
+           "policy": "tuned in the batch (hiccl_autotune_batch, coordinate descent over (collective, size class) "
+                     "on a 256-collective tuning batch of another seed)",
            "tuned": {f"{k[0]}/{SIZE_CLASSES[k[1]][0]}": v for k, v in table.items()},
-           "policy": policy, "policy_tuning_ms": policy_ms}
+           "tuning_batch_ms": tuning_ms}
+
     def timed(comms, mode, total_exec):
         b = Batch(comms, mode)
         b.run(st)
@@ -222,21 +207,19 @@ def batch_bench(torch, n=512, seed=4, reps=3):
         _progress(f"batch {mode}: {out[mode]['makespan_ms']:.3f} ms")
     for c in comms:
         c.close()
-    # the same collectives on the same buffers under the policy not chosen: what the choice is worth
-    other = "defaults" if policy == "table" else "table"
+    # the same collectives on the same buffers with the defaults (s = m = 1, default tile): what tuning is worth
     plain = []
     for i, (c, snd, rcv, S, _, name, dtype) in enumerate(items):
         d = S // (BATCH_P * 4)
-        s, m, tile = table[(name, _size_class(sizes[i]))] if other == "table" else (1, 1, 0)
         plain.append(CO.make(name, BATCH_P, dtype, [snd[r] for r in range(BATCH_P)], [rcv[r] for r in range(BATCH_P)],
-                             d, hierarchy=BATCH_H, stripe=s, pipeline=m, tile_bytes=tile))
+                             d, hierarchy=BATCH_H))
     plain_exec = 0
     for c in plain:
         info = c.plan_info()
         plain_exec += info["hbm_read"] + info["hbm_written"]
     for mode in ("serial", "persistent"):
-        out[f"{other}_{mode}"] = timed(plain, mode, plain_exec)
-        _progress(f"batch {other} {mode}: {out[f'{other}_{mode}']['makespan_ms']:.3f} ms")
+        out[f"defaults_{mode}"] = timed(plain, mode, plain_exec)
+        _progress(f"batch defaults {mode}: {out[f'defaults_{mode}']['makespan_ms']:.3f} ms")
     for c in plain:
         c.close()
     return out

@@ -388,6 +388,27 @@ int hiccl_autotune_model(hiccl_comm_t comm, const int* stripes, int nstripes, co
                          const size_t* tiles, int ntiles, int reps, int anchors, int top, void* stream,
                          int* best_stripe, int* best_pipe, size_t* best_tile, double* best_us, int* measured);
 
+/* Batched-context autotuner (stripe, pipeline and chunk size chosen for a
+ * batch of many collectives, Sec. 4.1 items 3 and 5 applied per class of
+ * members): `cls[i]` in [0, nclasses) assigns member i to a class (for
+ * example its collective type and size class). Coordinate descent over the
+ * classes on the median time (of `reps` runs after a warm run) of the merged
+ * launch of all `n` members in batch form `mode`: every class starts from
+ * stripes[0], pipes[0], tiles[0] (put the defaults first); each sweep visits
+ * the classes in turn and, per parameter, tries every other candidate with
+ * the rest fixed, keeping a change that shortens the batch by more than 1 %;
+ * it stops after `sweeps` sweeps or a sweep without change. Candidates that
+ * some member of the class cannot plan are skipped. The members are left
+ * initialized with the chosen values, which are written per class to
+ * best_stripe / best_pipe / best_tile [nclasses]; best_ms = the batch's
+ * median time under them. Members must satisfy hiccl_batch_create's rules.
+ * Errors: INVALID_ARG (empty lists, class out of range, first candidate not
+ * plannable), HIP. */
+int hiccl_autotune_batch(const hiccl_comm_t* comms, int n, const int* cls, int nclasses, const int* stripes,
+                         int nstripes, const int* pipes, int npipes, const size_t* tiles, int ntiles, int mode,
+                         int reps, int sweeps, void* stream, int* best_stripe, int* best_pipe, size_t* best_tile,
+                         double* best_ms);
+
 /* ----------------------------------------------------------------- serving */
 
 /* Admission and slot manager for a stream of collective requests

@@ -2338,6 +2338,114 @@ int hiccl_autotune(hiccl_comm_t comm, const int* stripes, int nstripes, const in
   return HICCL_SUCCESS;
 }
 
+// Batched-context autotuner: (stripe, pipeline, tile) per class of batch
+// members, chosen by coordinate descent on the time of the merged launch of
+// the whole batch, not of each collective alone. Every class starts from the
+// first candidate of each list; a sweep visits the classes in turn and, for
+// each of the three parameters, times every other value with the rest held
+// fixed, keeping a change only if it shortens the batch's median time by more
+// than 1 %. A candidate that some member of the class cannot plan (a stripe
+// that divides no group) is skipped. The members are left initialized with
+// the best assignment found.
+int hiccl_autotune_batch(const hiccl_comm_t* comms, int n, const int* cls, int nclasses, const int* stripes,
+                         int nstripes, const int* pipes, int npipes, const size_t* tiles, int ntiles, int mode,
+                         int reps, int sweeps, void* stream, int* best_stripe, int* best_pipe, size_t* best_tile,
+                         double* best_ms) {
+  if (!comms || n < 1 || !cls || nclasses < 1 || !stripes || !pipes || !tiles || nstripes < 1 || npipes < 1 ||
+      ntiles < 1 || reps < 1 || sweeps < 1)
+    return fail(HICCL_ERR_INVALID_ARG, "empty batch, classes or candidate set");
+  for (int i = 0; i < n; ++i) {
+    if (!comms[i]) return fail(HICCL_ERR_INVALID_ARG, "NULL communicator");
+    if (cls[i] < 0 || cls[i] >= nclasses) return fail(HICCL_ERR_INVALID_ARG, "class index out of range");
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  struct Pick {
+    int s, m, t;                   // indices into the candidate lists
+  };
+  std::vector<Pick> pick(size_t(nclasses), Pick{0, 0, 0});
+  auto plan_class = [&](int k, const Pick& q) -> bool {
+    bool ok = true;
+    for (int i = 0; i < n; ++i) {
+      if (cls[i] != k) continue;
+      Comm& c = comms[i]->c;
+      ok = ok && hiccl_set_stripe(comms[i], stripes[q.s]) == HICCL_SUCCESS &&
+           hiccl_set_pipeline(comms[i], pipes[q.m]) == HICCL_SUCCESS &&
+           hiccl_set_exec(comms[i], c.exec.mode, tiles[q.t], c.exec.grid, c.exec.order) == HICCL_SUCCESS &&
+           hiccl_init(comms[i]) == HICCL_SUCCESS;
+    }
+    return ok;
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  auto cleanup = [&]() {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  };
+  // median time (ms) of the merged launch, or a negative value if it cannot run
+  auto time_batch = [&]() -> double {
+    hiccl_batch_t b = nullptr;
+    if (hiccl_batch_create(comms, n, mode, &b) != HICCL_SUCCESS) return -1;
+    std::vector<float> ms;
+    bool ok = hiccl_batch_run(b, stream) == HICCL_SUCCESS && hiccl_batch_wait(b) == HICCL_SUCCESS;
+    for (int r = 0; r < reps && ok; ++r) {
+      ok = hipEventRecord(e0, st) == hipSuccess && hiccl_batch_run(b, stream) == HICCL_SUCCESS &&
+           hipEventRecord(e1, st) == hipSuccess && hiccl_batch_wait(b) == HICCL_SUCCESS;
+      float t = 0;
+      if (ok && hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms.push_back(t);
+    }
+    hiccl_batch_destroy(b);
+    if (!ok || ms.empty()) return -1;
+    std::sort(ms.begin(), ms.end());
+    return ms[ms.size() / 2];
+  };
+  for (int k = 0; k < nclasses; ++k)
+    if (!plan_class(k, pick[k])) {
+      cleanup();
+      return fail(HICCL_ERR_INVALID_ARG, "the first candidate cannot be planned for class " + std::to_string(k));
+    }
+  double best = time_batch();
+  if (best < 0) {
+    cleanup();
+    return fail(HICCL_ERR_HIP, "the batch could not be run");
+  }
+  for (int sw = 0; sw < sweeps; ++sw) {
+    bool changed = false;
+    for (int k = 0; k < nclasses; ++k) {
+      bool present = false;
+      for (int i = 0; i < n && !present; ++i) present = cls[i] == k;
+      if (!present) continue;
+      for (int dim = 0; dim < 3; ++dim) {
+        const int count = dim == 0 ? nstripes : (dim == 1 ? npipes : ntiles);
+        for (int v = 0; v < count; ++v) {
+          Pick q = pick[k];
+          int& slot = dim == 0 ? q.s : (dim == 1 ? q.m : q.t);
+          if (slot == v) continue;
+          slot = v;
+          const double t = plan_class(k, q) ? time_batch() : -1;
+          if (t >= 0 && t < 0.99 * best) {
+            best = t;
+            pick[k] = q;
+            changed = true;
+          } else if (!plan_class(k, pick[k])) {
+            cleanup();
+            return fail(HICCL_ERR_STATE, "could not restore class " + std::to_string(k));
+          }
+        }
+      }
+    }
+    if (!changed) break;
+  }
+  cleanup();
+  for (int k = 0; k < nclasses; ++k) {
+    if (best_stripe) best_stripe[k] = stripes[pick[k].s];
+    if (best_pipe) best_pipe[k] = pipes[pick[k].m];
+    if (best_tile) best_tile[k] = tiles[pick[k].t];
+  }
+  if (best_ms) *best_ms = best;
+  return HICCL_SUCCESS;
+}
+
 }  // extern "C"
 
 // ========================================================= payload formats

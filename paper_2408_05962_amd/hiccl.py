@@ -100,6 +100,8 @@ def lib():
                                C.POINTER(C.c_double)],
             "hiccl_autotune_model": [vp, pi, i, pi, i, C.POINTER(sz), i, i, i, i, vp, pi, pi, C.POINTER(sz),
                                      C.POINTER(C.c_double), pi],
+            "hiccl_autotune_batch": [C.POINTER(vp), i, pi, i, pi, i, pi, i, C.POINTER(sz), i, i, i, i, vp, pi, pi,
+                                     C.POINTER(sz), C.POINTER(C.c_double)],
             "hiccl_server_create": [sz, i, C.POINTER(vp)],
             "hiccl_server_admit": [vp, sz, C.POINTER(u64)],
             "hiccl_server_stream": [vp, u64, C.POINTER(vp)],
@@ -367,6 +369,24 @@ def autotune_model(comm: Comm, stripes, pipes, tiles, reps=3, anchors=4, top=2, 
 
 
 _live_servers: "weakref.WeakSet[Server]" = weakref.WeakSet()
+
+
+def autotune_batch(comms, classes, stripes, pipes, tiles, mode="persistent", reps=5, sweeps=2, stream=None):
+    """Per-class (stripe, pipeline, tile) by coordinate descent on the merged launch of the whole batch
+    (hiccl_autotune_batch); the members are left planned with the choice. Returns {"choice": [(s, m, tile)
+    per class], "ms": the batch's median time}."""
+    comms = list(comms)
+    ncls = max(classes) + 1
+    arr = (C.c_void_p * len(comms))(*[c.h for c in comms])
+    cl, _ = _ints(classes)
+    s, ns = _ints(stripes)
+    p, np_ = _ints(pipes)
+    t = (C.c_size_t * len(tiles))(*[int(v) for v in tiles])
+    bs, bp, bt = (C.c_int * ncls)(), (C.c_int * ncls)(), (C.c_size_t * ncls)()
+    ms = C.c_double()
+    check(lib().hiccl_autotune_batch(arr, len(comms), cl, ncls, s, ns, p, np_, t, len(tiles), BATCH.get(mode, mode),
+                                     int(reps), int(sweeps), stream_handle(stream), bs, bp, bt, C.byref(ms)))
+    return {"choice": [(bs[k], bp[k], bt[k]) for k in range(ncls)], "ms": ms.value}
 
 
 @atexit.register

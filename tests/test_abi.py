@@ -452,3 +452,26 @@ def test_run_static_checks_before_any_device_call(hc):
     assert lib.hiccl_run_static(c.h, None) == hc.ERR_INVALID_ARG
     assert b"static scratch" in lib.hiccl_last_error()
     c.close()
+
+
+def test_autotune_batch_argument_errors(hc):
+    """hiccl_autotune_batch refuses empty candidate lists and out-of-range classes before any device call."""
+    import ctypes as C
+    lib = hc.lib()
+    c = hc.Comm(4, "float32")
+    s, r = _bufs(4, 64), _bufs(4, 64)
+    from paper_2408_05962_amd import collectives as CO
+    CO.compose(c, "all_reduce", s, r, 16)
+    c.init()
+    arr = (C.c_void_p * 1)(c.h)
+    one = (C.c_int * 1)(1)
+    bad = (C.c_int * 1)(3)
+    tiles = (C.c_size_t * 1)(0)
+    out_i, out_p, out_t, ms = (C.c_int * 4)(), (C.c_int * 4)(), (C.c_size_t * 4)(), C.c_double()
+    args = lambda cls, ncls, ns: (arr, 1, cls, ncls, one, ns, one, 1, tiles, 1, 0, 1, 1, None, out_i, out_p, out_t,  # noqa: E731
+                                  C.byref(ms))
+    assert lib.hiccl_autotune_batch(*args(bad, 2, 1)) == hc.ERR_INVALID_ARG        # class 3 of 2
+    assert lib.hiccl_autotune_batch(*args(one, 2, 0)) == hc.ERR_INVALID_ARG        # no stripe candidate
+    assert lib.hiccl_autotune_batch(None, 0, one, 1, one, 1, one, 1, tiles, 1, 0, 1, 1, None, out_i, out_p, out_t,
+                                    C.byref(ms)) == hc.ERR_INVALID_ARG
+    c.close()

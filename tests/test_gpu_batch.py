@@ -242,3 +242,34 @@ def test_run_batch_memoized(torch_cuda, mode):
     for k, it in enumerate(items):
         H.check_result(it["name"], _got(it), it["sends"], it["dtype"], h=[2, 4], s=it["s"])
         it["comm"].close()
+
+
+def test_autotune_batch_choices_are_valid_and_results_exact(torch_cuda):
+    """hiccl_autotune_batch: per-class choices come from the candidate lists, the members are left planned
+    with them, and the batch then gives every collective's oracle result."""
+    torch = torch_cuda
+    from paper_2408_05962_amd import Batch, autotune_batch
+    items = _mix(torch, 12, seed=31)
+    for it in items:                       # start every member from the defaults the tuner starts from
+        it["comm"].set_stripe(1)
+        it["comm"].set_pipeline(1)
+        it["comm"].set_exec("persistent", 16384)
+        it["comm"].init()
+    classes = [H.SIX.index(it["name"]) % 3 for it in items]
+    res = autotune_batch([it["comm"] for it in items], classes, [1, 2], [1, 2, 4], [16384, 65536], reps=2,
+                         sweeps=1, stream=torch.cuda.current_stream())
+    assert len(res["choice"]) == max(classes) + 1 and res["ms"] > 0
+    for s, m, t in res["choice"]:
+        assert s in (1, 2) and m in (1, 2, 4) and t in (16384, 65536)
+    for it, k in zip(items, classes):
+        s, m, _ = res["choice"][k]
+        it["s"] = s
+        it["R"].zero_()
+    b = Batch([it["comm"] for it in items], "persistent")
+    b.run(torch.cuda.current_stream())
+    b.wait()
+    torch.cuda.synchronize()
+    b.close()
+    for it in items:
+        H.check_result(it["name"], _got(it), it["sends"], it["dtype"], h=[2, 4], s=it["s"])
+        it["comm"].close()
