@@ -171,7 +171,8 @@ int hiccl_set_share(hiccl_comm_t comm, int rank);
 
 /* Executor launch options (not a paper parameter): form (hiccl_exec_mode),
  * tile size in bytes (work unit of one workgroup; 0 = default: 64 KiB for
- * the persistent executor, 32 KiB for stage launches; at most 1 GiB;
+ * the persistent executor, 112 KiB for its fp8 tables, 32 KiB for stage
+ * launches; at most 1 GiB;
  * rounded to whole 16-byte vectors and whole fp8 scale blocks; hiccl_init
  * returns INVALID_ARG if a plan would need 2^31 tiles or more), grid (workgroups of the
  * persistent launch, or of each stage launch; 0 = default: one per compute

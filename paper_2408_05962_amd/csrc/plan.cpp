@@ -955,6 +955,14 @@ const char* hiccl_last_error(void) { return g_err.c_str(); }
 
 int hiccl_version(void) { return 10000; }
 
+// Default tile (measured best): 32 KiB for stage launches; 64 KiB for the persistent executor, whose
+// workgroups stream one tile with four worker waves, and 112 KiB for its fp8 tables, whose workgroups
+// have seven worker waves (two passes of 32 scale blocks per wave).
+static size_t default_tile_bytes(int mode, int dtype) {
+  if (mode == HICCL_EXEC_STAGED) return 32 * 1024;
+  return dtype == HICCL_FP8_E4M3 ? 112 * 1024 : 64 * 1024;
+}
+
 int hiccl_comm_create(int nranks, int dtype, hiccl_comm_t* out) {
   if (!out) return fail(HICCL_ERR_INVALID_ARG, "NULL output pointer");
   if (nranks < 1) return fail(HICCL_ERR_INVALID_ARG, "nranks must be >= 1");
@@ -964,6 +972,7 @@ int hiccl_comm_create(int nranks, int dtype, hiccl_comm_t* out) {
   h->c.P = nranks;
   h->c.dtype = dtype;
   h->c.hier = {nranks};
+  h->c.exec.tile_bytes = default_tile_bytes(h->c.exec.mode, dtype);
   *out = h;
   return HICCL_SUCCESS;
 }
@@ -1264,7 +1273,7 @@ int hiccl_set_exec(hiccl_comm_t comm, int mode, size_t tile_bytes, int grid, int
   unplan(comm->c);
   comm->c.exec.mode = mode;
   // default tile: 64 KiB for the persistent executor, 32 KiB for stage launches (measured best)
-  comm->c.exec.tile_bytes = tile_bytes ? tile_bytes : (mode == HICCL_EXEC_STAGED ? 32 * 1024 : 64 * 1024);
+  comm->c.exec.tile_bytes = tile_bytes ? tile_bytes : default_tile_bytes(mode, comm->c.dtype);
   comm->c.exec.grid = grid;
   comm->c.exec.order = order;
   return HICCL_SUCCESS;
