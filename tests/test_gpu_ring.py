@@ -164,7 +164,7 @@ def test_serving_mix_full_size_alone_and_in_the_mix(torch_cuda):
     """The measured serving mix itself (the bench's 48 templates, up to 256 MiB per rank, int32 / float32 /
     bf16): a stream of 300 requests served by the device ring, and again by concurrent slots, leaves every
     requested template's result bit-identical to the template run alone. The alone results equal the oracle
-    for every int32 / float32 template up to 4 MiB per rank."""
+    for every template up to 4 MiB per rank (bf16 reductions: the oracle's per-node requantization)."""
     torch = torch_cuda
     import bench as B
     import synth
@@ -179,7 +179,18 @@ def test_serving_mix_full_size_alone_and_in_the_mix(torch_cuda):
         alone.append(tp["rcv"].clone())
     torch.cuda.synchronize()
     for k, tp in enumerate(temps):
-        if tp["dtype"] == "bfloat16" or tp["S"] > 4 << 20:
+        if tp["S"] > 4 << 20:
+            continue
+        if tp["dtype"] == "bfloat16":
+            # bf16: copies move the bits unchanged; reductions equal the oracle's per-node widen / sum / narrow
+            sends = [x.view(np.uint16) for x in tp["snd"].cpu().numpy()]
+            out = alone[k].cpu().numpy().view(np.uint16)
+            if tp["name"] in ("reduce", "reduce_scatter", "all_reduce"):
+                exp = H.tree_order_payload(tp["name"], sends, tp["h"], tp["stripe"])
+            else:
+                exp = H.expected(tp["name"], sends)
+            for r, e in exp.items():
+                assert np.array_equal(out[r], np.asarray(e, np.uint16)), (k, tp["name"], "bf16", r)
             continue
         sends = list(tp["snd"].cpu().numpy())
         out = alone[k].cpu().numpy()
