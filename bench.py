@@ -285,7 +285,7 @@ def _time_comm(torch, c, reps=10, warm=2):
 
 def sweep_bench(torch):
     """Measurements beside the headline: pipeline depth, ring vs tree, two-step compositions, the
-    autotuners, Scatter / Gather, one rank's share, and the small All-Reduce's latency."""
+    autotuners, Scatter / Gather and one rank's share."""
     import numpy as np
 
     import synth
@@ -439,10 +439,30 @@ def sweep_bench(torch):
         _progress(f"rank shares {name}: {shares[name]}")
     out["one_rank_share_16r_64MiB_staged"] = shares
 
+    return out
+
+
+def small_all_reduce_bench(torch):
+    """The small All-Reduce of the latency-bound configuration: 4 ranks as {2,2}, 65,536 int32 per rank,
+    s = m = 1. Device time between events and host time from the call to the result, p50 / p99 over 50
+    runs, on each executor and through the device request ring; every form checked against the int32 sum."""
+    import numpy as np
+
+    import synth
+    from paper_2408_05962_amd import collectives as CO
+    st = torch.cuda.current_stream()
+
+    def mk(name, h, s, m, mode, p, dd, dtype):
+        snd = synth.device_buffers(dtype, 1, p, send_len(name, p, dd))
+        rcv = torch.zeros((p, recv_len(name, p, dd)), dtype=snd.dtype, device="cuda")
+        c = CO.make(name, p, dtype, [snd[r] for r in range(p)], [rcv[r] for r in range(p)], dd, hierarchy=h,
+                    stripe=s, pipeline=m, exec_mode=mode)
+        return c, snd, rcv
+
     # the small All-Reduce: 4 ranks as {2,2}, 65,536 int32 per rank, s = m = 1 (latency-bound)
     small = {}
     for mode in ("staged", "persistent"):
-        c, snd, rcv = mk("all_reduce", [2, 2], 1, 1, mode, p=4, dd=65536 // 4, dtype="int32")
+        c, snd, rcv = mk("all_reduce", [2, 2], 1, 1, mode, 4, 65536 // 4, "int32")
         lat = []
         for _ in range(3):
             c.run(st)
@@ -467,7 +487,7 @@ def sweep_bench(torch):
         del snd, rcv
     # the same request through the device request ring: host clock from append to the completion word
     from paper_2408_05962_amd import Server
-    c, snd, rcv = mk("all_reduce", [2, 2], 1, 1, "persistent", p=4, dd=65536 // 4, dtype="int32")
+    c, snd, rcv = mk("all_reduce", [2, 2], 1, 1, "persistent", 4, 65536 // 4, "int32")
     srv = Server(1 << 40, 1, ring=True, idle_ms=1000)
     lat = []
     for k in range(53):
@@ -485,9 +505,8 @@ def sweep_bench(torch):
                             "clock": "host, append to completion word"}
     c.close()
     del snd, rcv
-    out["small_all_reduce_4r_2x2_int32_256KiB"] = small
     _progress(f"small all-reduce: {small}")
-    return out
+    return small
 
 
 def _progress(msg):
@@ -807,9 +826,10 @@ def main():
     ap.add_argument("--serve-exec", default="persistent", choices=["staged", "persistent"],
                     help="executor of the serving templates")
     ap.add_argument("--no-precision", action="store_true", help="skip the precision form (bf16 / fp8)")
+    ap.add_argument("--no-small", action="store_true", help="skip the small All-Reduce (4 ranks, 256 KiB per rank)")
     ap.add_argument("--sweep", action="store_true",
                     help="also measure pipeline depth, ring vs tree, two-step compositions, the autotuners, "
-                         "Scatter / Gather, one rank's share and the small All-Reduce")
+                         "Scatter / Gather and one rank's share")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the virtual ranks of the hierarchy "
@@ -938,6 +958,8 @@ def main():
     if not args.no_precision:
         out["precision"] = precision_bench(torch)
         torch.cuda.empty_cache()
+    if not args.no_small:
+        out["small_all_reduce_4r_2x2_int32_256KiB"] = small_all_reduce_bench(torch)
     if args.sweep:
         out["sweep"] = sweep_bench(torch)
         torch.cuda.empty_cache()

@@ -1630,8 +1630,14 @@ struct StaticState {
 
 void static_state_free(StaticState* s) {
   if (!s) return;
-  // a copy from the host image may still be queued: let the device drain before the image goes
-  if (s->launched) (void)hipDeviceSynchronize();
+  // a copy from the host image may still be queued: let the device it ran on drain before the image goes
+  if (s->launched && s->ex.device >= 0) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(s->ex.device);
+    (void)hipDeviceSynchronize();
+    (void)hipSetDevice(cur);
+  }
   delete s;
 }
 
