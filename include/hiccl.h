@@ -234,10 +234,12 @@ int hiccl_wait(hiccl_comm_t comm);
  * counters and workspace live in a static device array of
  * HICCL_STATIC_SCRATCH_BYTES per GPU instead of library allocations; the
  * caller still passes the input and output buffers (at registration).
- * Each call copies the table (built on the host at the first call and kept
+ * A call copies the table (built on the host at the first call and kept
  * with the communicator) into the array on `stream`, which also resets
- * every counter, then launches the same kernels as hiccl_run; it calls no
- * hipMalloc / hipFree and ignores a workspace set by hiccl_set_workspace.
+ * every counter, unless the array still holds this communicator's table
+ * from its previous static call on the device; then it launches the same
+ * kernels as hiccl_run. It calls no hipMalloc / hipFree and ignores a
+ * workspace set by hiccl_set_workspace.
  * Every call on one GPU uses that GPU's one array, which keeps the last
  * call's contents: calls that overlap on one GPU (two streams, or the
  * device request ring of a server) race and give undefined results, so the

@@ -1621,15 +1621,29 @@ namespace hiccl {
 
 struct StaticState {
   Exe ex;                            // non-owning: every pointer lies inside one device's scratch array
-  std::vector<unsigned char> blob;   // host image of the tables; copied to scratch + table_off on every run
+  std::vector<unsigned char> blob;   // host image of the tables, copied to scratch + table_off
   uint64_t table_off = 0;
   void* base = nullptr;              // the scratch address the image was built for
+  uint64_t gen = 0;                  // this image's identity in static_owner
   hipStream_t stream = nullptr;
   bool launched = false;
 };
 
+// Per device, the image its scratch holds (a StaticState generation; 0 = none). A run whose image is
+// already there skips the copy: the tables are read-only, and the persistent executor's counters are
+// back at their initial values when its launch ends (its last workgroup resets them).
+constexpr int kStaticDevices = 64;
+static std::mutex static_mu;
+static uint64_t static_owner[kStaticDevices];
+static uint64_t static_gen = 0;
+
 void static_state_free(StaticState* s) {
   if (!s) return;
+  {
+    std::lock_guard<std::mutex> lock(static_mu);
+    for (uint64_t& o : static_owner)
+      if (o == s->gen) o = 0;
+  }
   // a copy from the host image may still be queued: let the device it ran on drain before the image goes
   if (s->launched && s->ex.device >= 0) {
     int cur = 0;
@@ -1731,6 +1745,8 @@ static int static_build(Comm& c, const StaticLayout& L, void* base, StaticState&
   put(L.cnt, img.cnt.data(), img.cnt.size() * 4);
   s.table_off = L.tasks;
   s.base = base;
+  std::lock_guard<std::mutex> lock(static_mu);
+  s.gen = ++static_gen;
   return 0;
 }
 
@@ -1782,9 +1798,17 @@ int hiccl_run_static(hiccl_comm_t comm, void* stream) {
   ex.grid = std::min<int>(device_grid(c.exec.grid), std::max<uint32_t>(1u, ex.ntiles));
   ex.stage_grid = c.exec.grid;
   ex.queues = uint32_t(std::max(1, std::min<int>(c.exec.queues, std::min<int>(kMaxQueues, ex.grid))));
-  // the table and fresh counters, then the kernels: everything on `stream`, in order
-  HIP_TRY(hipMemcpyAsync(static_cast<unsigned char*>(base) + s.table_off, s.blob.data(), s.blob.size(),
-                         hipMemcpyHostToDevice, st));
+  // the table and fresh counters unless the scratch still holds them, then the kernels: everything on
+  // `stream`, in order
+  {
+    std::lock_guard<std::mutex> lock(static_mu);
+    const int dev = ex.device;
+    if (dev < 0 || dev >= kStaticDevices || static_owner[dev] != s.gen) {
+      HIP_TRY(hipMemcpyAsync(static_cast<unsigned char*>(base) + s.table_off, s.blob.data(), s.blob.size(),
+                             hipMemcpyHostToDevice, st));
+      if (dev >= 0 && dev < kStaticDevices) static_owner[dev] = s.gen;
+    }
+  }
   if (int rc = launch(ex, st)) return rc;
   s.stream = st;
   s.launched = true;
