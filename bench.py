@@ -952,7 +952,8 @@ def main():
                                  "value": round(len(SIX) * S_BYTES / alt["step_ms"] / 1e6, 2),
                                  "exec_GBps": round(alt["kern_bytes"] / alt["kern_ms"] / 1e6, 1),
                                  "hbm_frac": round(alt["kern_bytes"] / alt["kern_ms"] / 1e6 / PEAK_HBM, 4),
-                                 "per_collective_ms": {n: v["ms"] for n, v in alt["per"].items()}}
+                                 "per_collective_ms": {n: v["ms"] for n, v in alt["per"].items()},
+                                 "per_collective_hbm_frac": {n: v["hbm_frac"] for n, v in alt["per"].items()}}
     del bufs
     torch.cuda.empty_cache()
     if not args.no_precision:

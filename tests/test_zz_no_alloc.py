@@ -119,3 +119,26 @@ def test_static_after_run_and_run_after_static(torch_cuda):
         assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), f"call {k} ({how}) differs"
     for x in comms:
         x.close()
+
+
+def test_static_empty_and_tiny(torch_cuda):
+    """Edge cases through the allocation-free entry point: an empty collective (count 0: no task, no
+    launch) and a ragged 3-element one, each against hiccl_run."""
+    torch = torch_cuda
+    from paper_2408_05962_amd import collectives as CO
+    st = torch.cuda.current_stream()
+    for name, p, h, d in (("all_reduce", 4, [2, 2], 0), ("reduce_scatter", 8, [2, 4], 3), ("all_to_all", 4, [4], 1)):
+        n = max(1, H.send_len(name, p, d))
+        X = torch.arange(p * n, dtype=torch.int32, device="cuda").reshape(p, n)
+        outs = []
+        for how in ("run", "static"):
+            R = torch.full((p, max(1, H.recv_len(name, p, d))), -5, dtype=torch.int32, device="cuda")
+            c = CO.make(name, p, "int32", [X[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=h)
+            (c.run if how == "run" else c.run_static)(st)
+            c.wait()
+            torch.cuda.synchronize()
+            outs.append(R.cpu().numpy())
+            c.close()
+        assert np.array_equal(outs[0], outs[1]), name
+        if d == 0:
+            assert np.all(outs[1] == -5)          # nothing written
