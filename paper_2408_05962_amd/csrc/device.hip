@@ -659,17 +659,18 @@ struct TileRef {
   uint32_t k, nsucc, succ_begin, ntiles, comm;
 };
 
-// Retire one tile: the last tile of its task releases the task's successors
-// and, when the task is its collective's last, stamps the completion time.
+// Retire n tiles of one task (consecutive tiles a workgroup ran): the last
+// tile of the task releases its successors and, when the task is its
+// collective's last, stamps the completion time.
 // A task that releases nothing (no successors, no stamp) needs no counter
 // traffic at all. The tile's data stores are device-coherent and complete
 // (every worker wave that ran it waited before the workgroup barrier that
 // precedes this call), so counting it is the release.
-__device__ __forceinline__ void retire(const ExecArgs& a, const TileRef& r) {
+__device__ __forceinline__ void retire(const ExecArgs& a, const TileRef& r, uint32_t n = 1) {
   if (!r.nsucc && !a.times) return;
   if (r.ntiles > 1) {
-    uint32_t old = __hip_atomic_fetch_add(&a.done[r.k], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old + 1 != r.ntiles) return;
+    uint32_t old = __hip_atomic_fetch_add(&a.done[r.k], n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old + n != r.ntiles) return;
   }
   const uint32_t b = r.succ_begin, e = b + r.nsucc;
   for (uint32_t s = b; s < e; ++s)
@@ -778,6 +779,7 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
   const bool lead = threadIdx.x == BLOCK;                                  // the scheduler's lane 0
   Claim c{blockIdx.x % a.queues, 0, 0, 0};
   TileRef cur_ref{}, prev_ref{};
+  uint32_t held = 0;          // retired tiles of prev_ref's task not yet counted (scheduler lane)
   if (sched) {
     // nothing of this workgroup is in flight yet: a full wait cannot block on itself
     uint32_t tl_l = kNoTile;
@@ -813,7 +815,16 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
         const uint32_t nx = __builtin_amdgcn_readfirstlane(nx_l);
         const uint2 o_l = nx != kNoTile ? a.order[nx] : make_uint2(0u, 0u);   // in flight during the retire below
         const uint32_t k_l = o_l.x;
-        if (lead && have_prev) retire(a, prev_ref);
+        if (lead && have_prev) {
+          // the workers now run a tile of the same task: its task cannot complete before that tile
+          // retires, so count the two together then (one atomic for consecutive tiles of a task)
+          if (cur_ref.k == prev_ref.k) {
+            ++held;
+          } else {
+            retire(a, prev_ref, held + 1);
+            held = 0;
+          }
+        }
         const uint32_t knx = __builtin_amdgcn_readfirstlane(k_l);
         uint32_t post = kNoTile;
         if (nx != kNoTile) {
@@ -836,7 +847,10 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
       } else {
         // the workers idle this iteration; everything of ours has retired once
         // tile i-1 has, so wait in full, then post tl again in the other slot
-        if (lead && have_prev) retire(a, prev_ref);
+        if (lead && have_prev) {
+          retire(a, prev_ref, held + 1);
+          held = 0;
+        }
         stage_desc(next, &s_task[cur], lane);
         uint32_t post = kNoTile;
         if (lead) post = wait_ready(a, cur_ref.k, s_task[cur].npred) ? tl : kNoTile;
@@ -859,7 +873,7 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
     __syncthreads();
   }
   if (sched) {
-    if (lead && have_prev) retire(a, prev_ref);
+    if (lead && have_prev) retire(a, prev_ref, held + 1);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
