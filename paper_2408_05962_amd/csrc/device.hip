@@ -1299,7 +1299,8 @@ struct Image {
 // Build the host image of the merged table of `plans` and fill the host-side
 // fields of `ex` (stage boundaries, launch shape); no device pointer is set.
 static int build_image(const std::vector<const Plan*>& plans, const std::vector<uint64_t>& ws_base, int mode,
-                       int grid, uint32_t spin_limit, Exe& ex, int queues, int batch, int merge, Image& img) {
+                       int grid, uint32_t spin_limit, Exe& ex, int queues, int batch, int merge, Image& img,
+                       bool group = false) {
   ex.mode = mode;
   ex.spin_limit = spin_limit;
   ex.ncomm = uint32_t(plans.size());
@@ -1310,10 +1311,36 @@ static int build_image(const std::vector<const Plan*>& plans, const std::vector<
   std::vector<Ref> refs;
   for (uint32_t p = 0; p < plans.size(); ++p)
     for (uint32_t i = 0; i < plans[p]->tasks.size(); ++i) refs.push_back({p, i});
+  // Launch key of a task: its stage; for the stage launches of one large plan, (channel group, stage).
+  // Running every stage for the first channels, then every stage for the next ones, lets a stage read
+  // its producer's output while the caches still hold it; it pays once a stage moves more than the
+  // caches hold (measured: float32 All-Reduce at 2^28 elements per rank 11.8 -> 10.9 ms with four
+  // groups), and costs where launches would get short (the 64 MiB headline: 2.63 -> 2.80 ms with two).
+  // So: the largest power of two G <= 4 with G * 2 GiB <= the plan's bytes per stage. Grouping is used
+  // only when every dependency edge runs from an earlier launch to a later one.
+  std::vector<int> gkey;
+  if (group && plans.size() == 1 && mode == HICCL_EXEC_STAGED && plans[0]->nstages > 0) {
+    const Plan& P = *plans[0];
+    const uint64_t per_stage = (P.hbm_read + P.hbm_written) / uint64_t(P.nstages);
+    int groups = 1;
+    while (groups < 4 && per_stage >= uint64_t(2 * groups) * (uint64_t(2) << 30)) groups *= 2;
+    int nch = 1, ns = 1;
+    for (const Task& t : P.tasks) {
+      nch = std::max(nch, t.channel + 1);
+      ns = std::max(ns, t.stage + 1);
+    }
+    if (groups > 1) gkey.resize(P.tasks.size());
+    for (size_t i = 0; i < gkey.size(); ++i) gkey[i] = (P.tasks[i].channel * groups / nch) * ns + P.tasks[i].stage;
+    bool ok = true;
+    for (size_t i = 0; i < gkey.size() && ok; ++i)
+      for (int pr : P.tasks[i].preds) ok = ok && gkey[pr] < gkey[i];
+    if (!ok) gkey.clear();
+  }
+  auto stage_of = [&](const Ref& r) { return gkey.empty() ? plans[r.plan]->tasks[r.idx].stage : gkey[r.idx]; };
   // stage launches need the table grouped by stage, whatever each plan's claim order
   if ((plans.size() > 1 && merge == 0) || mode == HICCL_EXEC_STAGED) {
     std::stable_sort(refs.begin(), refs.end(), [&](const Ref& x, const Ref& y) {
-      return plans[x.plan]->tasks[x.idx].stage < plans[y.plan]->tasks[y.idx].stage;
+      return stage_of(x) < stage_of(y);
     });
   } else if (plans.size() > 1) {
     std::vector<uint64_t> bytes(plans.size());
@@ -1370,7 +1397,7 @@ static int build_image(const std::vector<const Plan*>& plans, const std::vector<
     d.comm = refs[i].plan;
     for (uint32_t q = 0; q < t.ntiles; ++q) tile_task.push_back(uint32_t(i));
     comm_n[refs[i].plan] += 1;
-    nstages = std::max(nstages, t.stage + 1);
+    nstages = std::max(nstages, stage_of(refs[i]) + 1);
     if (t.dtype == HICCL_BFLOAT16 || t.dtype == HICCL_FP8_E4M3) ex.narrow = true;
   }
   ex.ntasks = uint32_t(nt);
@@ -1378,8 +1405,7 @@ static int build_image(const std::vector<const Plan*>& plans, const std::vector<
   // stage boundaries in the merged table (stage-sorted when one plan is stage-ordered or several are merged)
   ex.stage_tile_begin.assign(nstages + 1, ex.ntiles);
   for (int i = int(nt) - 1; i >= 0; --i) {
-    const Task& t = plans[refs[i].plan]->tasks[refs[i].idx];
-    ex.stage_tile_begin[t.stage] = h[i].first_tile;
+    ex.stage_tile_begin[stage_of(refs[i])] = h[i].first_tile;
   }
   for (int s = nstages - 1; s >= 0; --s) ex.stage_tile_begin[s] = std::min(ex.stage_tile_begin[s], ex.stage_tile_begin[s + 1]);
 
@@ -1394,7 +1420,7 @@ static int build_image(const std::vector<const Plan*>& plans, const std::vector<
     order[tl] = make_uint2(tile_task[tl], uint32_t(tl - h[tile_task[tl]].first_tile));
   bool stage_sorted = true;
   for (size_t i = 1; i < nt && stage_sorted; ++i)
-    stage_sorted = plans[refs[i - 1].plan]->tasks[refs[i - 1].idx].stage <= plans[refs[i].plan]->tasks[refs[i].idx].stage;
+    stage_sorted = stage_of(refs[i - 1]) <= stage_of(refs[i]);
   const uint32_t spread = mode == HICCL_EXEC_STAGED ? 1u : uint32_t(std::max(1, batch));
   // Stage launches run every other stage's tiles in reverse: a stage's last tiles wrote the lines that
   // are still in the caches, and the next stage's first tiles read them. (Any order within a stage is valid.)
@@ -1428,12 +1454,12 @@ static void patch_extra(Image& img, const uint64_t* d_extra) {
 
 static int upload(const std::vector<const Plan*>& plans, const std::vector<uint64_t>& ws_base, int mode, int grid,
                   uint32_t spin_limit, bool with_times, Exe& ex, int queues = kMaxQueues,
-                  int batch = HICCL_CLAIM_BATCH, int merge = 0) {
+                  int batch = HICCL_CLAIM_BATCH, int merge = 0, bool group = false) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
   ex.device = dev;
   Image img;
-  if (int rc = build_image(plans, ws_base, mode, grid, spin_limit, ex, queues, batch, merge, img)) return rc;
+  if (int rc = build_image(plans, ws_base, mode, grid, spin_limit, ex, queues, batch, merge, img, group)) return rc;
   auto alloc_copy = [&](void** dptr, const void* src, size_t bytes) -> int {
     HIP_TRY(hipMalloc(dptr, std::max<size_t>(bytes, 16)));
     if (bytes) HIP_TRY(hipMemcpy(*dptr, src, bytes, hipMemcpyHostToDevice));
@@ -1534,7 +1560,7 @@ static int ensure_device(Comm& c) {
     ws = uint64_t(reinterpret_cast<uintptr_t>(s->ws));
   }
   int rc = upload({&c.plan}, {ws}, c.exec.mode, c.exec.grid, c.exec.spin_limit, false, s->exe, c.exec.queues,
-                  c.exec.batch);
+                  c.exec.batch, 0, true);
   if (!rc && hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) != hipSuccess)
     rc = fail(HICCL_ERR_HIP, "event creation failed");
   if (rc) {
@@ -1731,7 +1757,7 @@ static int static_build(Comm& c, const StaticLayout& L, void* base, StaticState&
   const uint64_t b = uint64_t(reinterpret_cast<uintptr_t>(base));
   Image img;
   if (int rc = build_image({&c.plan}, {b}, c.exec.mode, c.exec.grid, c.exec.spin_limit, s.ex, c.exec.queues,
-                           c.exec.batch, 0, img))
+                           c.exec.batch, 0, img, true))
     return rc;
   unsigned char* B = static_cast<unsigned char*>(base);
   s.ex.d_tasks = reinterpret_cast<DevTask*>(B + L.tasks);
