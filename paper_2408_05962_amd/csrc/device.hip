@@ -1311,13 +1311,14 @@ static int build_image(const std::vector<const Plan*>& plans, const std::vector<
   std::vector<Ref> refs;
   for (uint32_t p = 0; p < plans.size(); ++p)
     for (uint32_t i = 0; i < plans[p]->tasks.size(); ++i) refs.push_back({p, i});
-  // Launch key of a task: its stage; for one large plan, (channel group, stage), which orders the stage
-  // launches and the persistent executor's claims. Running every stage for the first channels, then
-  // every stage for the next ones, lets a stage read its producer's output while the caches still hold it; it pays once a stage moves more than the
-  // caches hold (measured: float32 All-Reduce at 2^28 elements per rank 11.8 -> 10.9 ms with four
-  // groups), and costs where launches would get short (the 64 MiB headline: 2.63 -> 2.80 ms with two).
-  // So: the largest power of two G <= 4 with G * 2 GiB <= the plan's bytes per stage. Grouping is used
-  // only when every dependency edge runs from an earlier launch to a later one.
+  // Launch key of a task: its stage; for one large plan, (channel group, stage), which orders the
+  // stage launches and the persistent executor's claims. Running every stage for the first channels,
+  // then every stage for the next ones, lets a stage read its producer's output while the caches still
+  // hold it. That pays once a stage moves more than the caches hold (measured: float32 All-Reduce at
+  // 2^28 elements per rank 11.8 -> 10.9 ms with four groups), and costs where launches would get short
+  // (the 64 MiB headline: 2.63 -> 2.80 ms with two). So: the largest power of two G <= 4 with
+  // G * 2 GiB <= the plan's bytes per stage. Grouping is used only when every dependency edge runs from
+  // an earlier launch to a later one, which also keeps the claim order topological.
   std::vector<int> gkey;
   if (group && plans.size() == 1 && plans[0]->nstages > 0) {
     const Plan& P = *plans[0];
