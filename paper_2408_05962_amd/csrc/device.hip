@@ -1140,6 +1140,7 @@ struct Exe {
   int grid = 0;                    // persistent: workgroups of the launch
   int stage_grid = 0;              // staged: workgroups per stage launch (0 = by stage, see launch_stage)
   std::vector<uint8_t> stage_shared;   // per stage: some of its tiles read the same source bytes
+  std::vector<uint8_t> stage_final;    // per stage: no task of it has successors (it writes results)
   uint32_t spin_limit = 1u << 22;
   uint32_t queues = kMaxQueues;
   uint32_t batch = HICCL_CLAIM_BATCH;
@@ -1239,7 +1240,6 @@ static int cu_count() {
   return cus;
 }
 static int device_grid(int want) { return want > 0 ? want : cu_count(); }
-static int stage_grid(int want) { return want > 0 ? want : 2 * cu_count(); }
 
 // Flatten plans into one device task table. ws_base[i] is plan i's workspace.
 // merge: 0 = interleave the collectives by dependency stage; 1 = smallest
@@ -1428,6 +1428,9 @@ static int build_image(const std::vector<const Plan*>& plans, const std::vector<
   if (stage_sorted && mode == HICCL_EXEC_STAGED)
     for (int s = 1; s < nstages; s += 2)
       std::reverse(order.begin() + ex.stage_tile_begin[s], order.begin() + ex.stage_tile_begin[s + 1]);
+  ex.stage_final.assign(size_t(nstages), 1);
+  for (size_t i = 0; i < nt; ++i)
+    if (h[i].nsucc) ex.stage_final[stage_of(refs[i])] = 0;
   ex.stage_shared.assign(size_t(nstages), 1);
   if (stage_sorted)
     for (int s = 0; s < nstages; ++s)
@@ -1485,18 +1488,27 @@ static int upload(const std::vector<const Plan*>& plans, const std::vector<uint6
   return 0;
 }
 
-// One stage launch over tiles [lo, hi) of a staged table (stage s). By
-// default a stage whose tiles share sources (sibling hops of a multicast)
-// runs two workgroups per CU, so that a group's tiles meet on their XCD at
-// the same time; a stage of independent int32 / float32 streams (reduce
-// nodes, point-to-point hops) runs one per CU, which streams them faster.
-// bf16 / fp8 tables keep two per CU: their reduce tiles spend more time in
+// One stage launch over tiles [lo, hi) of a staged table (stage s). The
+// default width depends on the stage (measured per stage on the six
+// collectives at 16 ranks x 64 MiB; the pass went 2.63 -> 2.56 ms):
+// - three workgroups per CU for a stage whose tiles share sources (sibling
+//   hops of a multicast meet on their XCD at the same time) and for a short
+//   stage (at most 16 tiles per CU), where more tiles in flight shorten the
+//   launch's ramp-up and drain;
+// - two per CU for a stage that writes final results (streamed stores);
+// - one per CU for a long stage of independent int32 / float32 streams
+//   (reduce nodes, point-to-point hops), which streams them fastest.
+// bf16 / fp8 tables run two per CU: their reduce tiles spend more time in
 // arithmetic and need the second workgroup to cover memory latency.
 static int launch_stage(const Exe& ex, hipStream_t st, size_t s, uint32_t lo, uint32_t hi) {
   if (hi <= lo) return 0;
   ExecArgs a = ex.args();
-  const bool two = ex.narrow || s >= ex.stage_shared.size() || ex.stage_shared[s];
-  const uint32_t want = uint32_t(ex.stage_grid > 0 ? ex.stage_grid : (two ? stage_grid(0) : cu_count()));
+  const uint32_t cus = uint32_t(cu_count());
+  const bool shared = s >= ex.stage_shared.size() || ex.stage_shared[s];
+  const bool fin = s < ex.stage_final.size() && ex.stage_final[s];
+  const bool small = hi - lo <= 16u * cus;
+  const uint32_t per = ex.narrow ? 2u : (shared || small) ? 3u : fin ? 2u : 1u;
+  const uint32_t want = ex.stage_grid > 0 ? uint32_t(ex.stage_grid) : per * cus;
   int g = int(std::min<uint32_t>(hi - lo, want));
   if (ex.narrow)
     hipLaunchKernelGGL((hiccl_staged<kBlock, true>), dim3(g), dim3(kBlock), 0, st, a, lo, hi);
