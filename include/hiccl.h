@@ -325,15 +325,23 @@ int hiccl_validate_host(hiccl_comm_t comm, uint64_t seed, int norders);
 /* ---------------------------------------------------------------- batching */
 
 typedef enum {
-  HICCL_BATCH_PERSISTENT = 0,  /* all task tables merged into one persistent launch */
+  HICCL_BATCH_PERSISTENT = 0,  /* all task tables merged into one persistent launch, members in groups
+                                  of about 1 GiB of executed bytes, claimed group after group */
   HICCL_BATCH_GRAPH = 1,       /* captured once into a hipGraph and replayed: 4 parallel branches,
                                   balanced by executed bytes, each running its collectives as stage
                                   launches on a quarter of the device */
   HICCL_BATCH_SERIAL = 2,      /* one launch per collective on the stream (reference form) */
-  HICCL_BATCH_PERSISTENT_SJF = 3, /* one merged launch, smallest collectives claimed first */
+  HICCL_BATCH_PERSISTENT_SJF = 3, /* one merged launch, smallest collectives claimed first (grouped
+                                     the same way, in order of executed bytes) */
   HICCL_BATCH_STAGED = 4          /* task tables merged by dependency stage; one launch per stage for
-                                     all collectives together (completion = end of a collective's last stage) */
+                                     a group of members (about 4 GiB of executed bytes), group after group
+                                     (completion = end of a collective's last stage launch) */
 } hiccl_batch_mode;
+/* The merged forms (PERSISTENT, PERSISTENT_SJF, STAGED) run their members in
+ * groups so that a collective's stages run close together and read what the
+ * previous stage wrote from the caches. The environment variable
+ * HICCL_BATCH_GROUP_MB, read when a batch is built, overrides the group size
+ * (MiB of executed bytes; 0 = all members in one group). */
 
 /* Group initialized communicators (any mix of dtypes and hierarchies) into
  * one batch. Members run with no ordering between them, so they must be

@@ -52,10 +52,17 @@ def _got(it, p=8):
     return {r: out[r] for r in ranks}
 
 
-@pytest.mark.parametrize("mode", ["persistent", "graph", "serial", "persistent_sjf", "staged"])
-def test_batch_matches_oracle_and_alone(torch_cuda, mode):
+@pytest.mark.parametrize("mode,group_mb", [("persistent", None), ("graph", None), ("serial", None),
+                                           ("persistent_sjf", None), ("staged", None),
+                                           ("persistent", 1), ("persistent_sjf", 1), ("staged", 1)])
+def test_batch_matches_oracle_and_alone(torch_cuda, mode, group_mb, monkeypatch):
+    """group_mb = 1: the merged forms split the batch into groups of about 1 MiB of executed bytes (most
+    members form a group of their own), so stage launches and claims run group after group (persistent:
+    along diagonals of group and stage)."""
     torch = torch_cuda
     from paper_2408_05962_amd import Batch
+    if group_mb is not None:
+        monkeypatch.setenv("HICCL_BATCH_GROUP_MB", str(group_mb))
     items = _mix(torch, 24, seed=11)
     alone = []
     for it in items:
@@ -153,9 +160,10 @@ def test_staged_batch_of_program_ordered_plans(torch_cuda):
 def test_batch_512_full_size(torch_cuda):
     """The measured batch itself: 512 collectives over 8 ranks as {2,4}, 4 KiB-64 MiB per rank, float32 /
     int32, with the bench's seeds and its default policy (s = m = 1, default tile). In one persistent launch
-    and in the captured graph every result is bit-identical (compared on the device) to the same collective
+    (batch order and smallest first), in the captured graph and in merged stage launches every result is bit-identical (compared on the device) to the same collective
     run alone; those alone results equal the oracle for every collective up to 4 MiB per rank and for the
-    largest collective of each type."""
+    largest collective of each type. The merged forms run the batch in groups of members (1 GiB of executed
+    bytes for the persistent launch, 4 GiB for stage launches), so several groups are exercised."""
     torch = torch_cuda
     import bench as B
     import synth
@@ -192,7 +200,7 @@ def test_batch_512_full_size(torch_cuda):
         # (the float32 tree-order emulation is skipped above 4 MiB per rank to bound the host time)
         H.check_result(it["name"], {r: out[r] for r in ranks}, sends, it["dtype"], h=B.BATCH_H, s=1,
                        order_exact=it["S"] <= 4 << 20)
-    for mode in ("persistent", "graph"):
+    for mode in ("persistent", "graph", "staged", "persistent_sjf"):
         for it in items:
             it["rcv"].zero_()
         b = Batch([it["c"] for it in items], mode)
