@@ -1330,8 +1330,14 @@ static int build_image(const std::vector<const Plan*>& plans, const std::vector<
   // hold it. That pays once a stage moves more than the caches hold (measured: float32 All-Reduce at
   // 2^28 elements per rank 11.8 -> 10.9 ms with four groups), and costs where launches would get short
   // (the 64 MiB headline: 2.63 -> 2.80 ms with two). So: the largest power of two G <= 4 with
-  // G * 2 GiB <= the plan's bytes per stage. Grouping is used only when every dependency edge runs from
-  // an earlier launch to a later one, which also keeps the claim order topological.
+  // G * 2 GiB <= the plan's bytes per stage. A smaller plan claimed by the persistent executor whose
+  // executed bytes are mostly reductions takes two groups claimed along diagonals (key (g + s) * S + S -
+  // 1 - s, S stages: group 0's stage s beside group 1's stage s - 1), so the partial sums a stage wrote
+  // are still cached when the next stage reads them and neither group waits at a stage boundary
+  // (measured at 16 ranks x 64 MiB: Reduce 0.424 -> 0.411 ms, Reduce-Scatter 0.444 -> 0.426 ms,
+  // All-Reduce 0.706 -> 0.694 ms; the copy-only collectives did not gain). Grouping is used only when
+  // every dependency edge runs from an earlier launch to a later one, which also keeps the claim order
+  // topological.
   std::vector<int> gkey;
   if (group && plans.size() == 1 && plans[0]->nstages > 0) {
     const Plan& P = *plans[0];
@@ -1343,8 +1349,21 @@ static int build_image(const std::vector<const Plan*>& plans, const std::vector<
       nch = std::max(nch, t.channel + 1);
       ns = std::max(ns, t.stage + 1);
     }
+    bool diag = false;
+    if (groups == 1 && mode == HICCL_EXEC_PERSISTENT && nch > 1) {
+      uint64_t red = 0;
+      for (const Task& t : P.tasks)
+        if (t.kind != kCopy) red += t.count * elem_size(t.dtype) * (t.src.size() + 1);
+      if (2 * red >= P.hbm_read + P.hbm_written) {
+        groups = 2;
+        diag = true;
+      }
+    }
     if (groups > 1) gkey.resize(P.tasks.size());
-    for (size_t i = 0; i < gkey.size(); ++i) gkey[i] = (P.tasks[i].channel * groups / nch) * ns + P.tasks[i].stage;
+    for (size_t i = 0; i < gkey.size(); ++i) {
+      const int g = P.tasks[i].channel * groups / nch, st = P.tasks[i].stage;
+      gkey[i] = diag ? (g + st) * ns + (ns - 1 - st) : g * ns + st;
+    }
     bool ok = true;
     for (size_t i = 0; i < gkey.size() && ok; ++i)
       for (int pr : P.tasks[i].preds) ok = ok && gkey[pr] < gkey[i];
