@@ -1119,7 +1119,7 @@ __global__ __launch_bounds__(BLOCK) void hiccl_ring(RingArgs r) {
 constexpr int kBlock = 256;
 // Worker threads of a persistent workgroup for tables with bf16 / fp8 tasks: their reduce tiles spend
 // more time in arithmetic, and seven worker waves per CU hide more of it than four (measured: fp8
-// Reduce-Scatter at 2^28 elements per rank 2.37 -> 2.03 ms, with 112 KiB tiles). The kernel's 211
+// Reduce-Scatter at 2^28 elements per rank 2.37 -> 2.03 ms, with 112 KiB tiles). The kernel's 217
 // registers allow eight waves per CU, so 7 workers and the scheduler fill it.
 constexpr int kNarrowBlock = 448;
 constexpr int kGraphBranches = 4;     // parallel branches of the captured batch graph
