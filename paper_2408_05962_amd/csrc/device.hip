@@ -1317,7 +1317,7 @@ static int build_image(const std::vector<const Plan*>& plans, const std::vector<
   ex.mode = mode;
   ex.spin_limit = spin_limit;
   ex.ncomm = uint32_t(plans.size());
-  // merged order: by stage, then collective, then the plan's own order
+  // table order: by launch key (below), then member, then the plan's own order
   struct Ref {
     uint32_t plan, idx;
   };
