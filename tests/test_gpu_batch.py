@@ -90,6 +90,47 @@ def test_batch_matches_oracle_and_alone(torch_cuda, mode, group_mb, monkeypatch)
         it["comm"].close()
 
 
+@pytest.mark.parametrize("mode", ["persistent", "persistent_sjf", "staged"])
+def test_grouped_batch_completes_group_by_group(torch_cuda, mode, monkeypatch):
+    """With groups of about 1 MiB of executed bytes, the merged forms finish their members in group order:
+    batch order for the persistent launch and the stage launches, smallest first for persistent_sjf. The
+    members are 32 int32 All-Reduces over 8 ranks whose sizes fall along the batch order, so smallest
+    first reverses it. The first eight members to run must finish, in median, before the last eight, and
+    every result equals the oracle."""
+    torch = torch_cuda
+    import synth
+    from paper_2408_05962_amd import Batch
+    from paper_2408_05962_amd import collectives as CO
+    monkeypatch.setenv("HICCL_BATCH_GROUP_MB", "1")
+    p, h, n = 8, [2, 4], 32
+    items = []
+    for i in range(n):
+        d = 4096 * (n - i)                       # buffers of 4 MiB down to 128 KiB per rank
+        sends = [np.asarray(x) for x in synth.rank_buffers("int32", 6, i, p, H.send_len("all_reduce", p, d))]
+        S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+        R = torch.zeros((p, H.recv_len("all_reduce", p, d)), dtype=S.dtype, device="cuda")
+        c = CO.make("all_reduce", p, "int32", [S[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=h)
+        c.set_spin_limit(1 << 20)
+        items.append({"comm": c, "S": S, "R": R, "sends": sends})
+    b = Batch([it["comm"] for it in items], mode)
+    st = torch.cuda.current_stream()
+    for rep in range(2):
+        for it in items:
+            it["R"].zero_()
+        b.run(st)
+        b.wait()
+        torch.cuda.synchronize()
+        times = np.array(b.times_ns(), dtype=np.float64)
+        run_order = times if mode != "persistent_sjf" else times[::-1]
+        assert np.median(run_order[:8]) < np.median(run_order[-8:]), (mode, rep, times.tolist())
+    for it in items:
+        out = it["R"].cpu().numpy()
+        H.check_result("all_reduce", {r: out[r] for r in range(p)}, it["sends"], "int32", h=h)
+    b.close()
+    for it in items:
+        it["comm"].close()
+
+
 @pytest.mark.parametrize("kind", ["exhaustive", "model"])
 def test_autotuners_pick_a_valid_configuration(torch_cuda, kind):
     torch = torch_cuda
