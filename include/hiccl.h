@@ -220,7 +220,11 @@ int hiccl_run(hiccl_comm_t comm, void* stream);
 /* wait() of Listing 2: block the host until the last run's buffers may be
  * reused. Returns TIMEOUT if the executor gave up a dependency wait. After
  * hiccl_run_static it synchronizes that run's stream and reads the status
- * word in the device's static scratch (the last static run's on the device). */
+ * word in the device's static scratch (the last static run's on the device).
+ * Debug check: while the environment variable HICCL_DEBUG is non-zero, this
+ * call (and hiccl_batch_wait) also reads back every counter of the task
+ * table and returns STATE if one is not where the next run expects it
+ * (dependency, tile and claim counters zero, task counts restored). */
 int hiccl_wait(hiccl_comm_t comm);
 
 /* Size of the static device scratch of hiccl_run_static: 64 MiB, held by

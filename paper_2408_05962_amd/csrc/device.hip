@@ -1611,6 +1611,49 @@ static int launch(const Exe& ex, hipStream_t st) {
   return 0;
 }
 
+// Debug check, on while the environment variable HICCL_DEBUG is set to a non-zero value: after a run,
+// every counter of the table is back where the next run expects it (the last workgroup of a persistent
+// launch resets them; stage launches never touch them). Dependency and tile counters, claim counters and
+// the exit / abort words are zero, and each collective's count of tasks left equals its task count. A
+// counter left behind would make the next run start early or wait forever, so it is an error (STATE).
+// The check copies the counters to the host in fixed-size pieces: it allocates nothing.
+static bool debug_checks() {
+  const char* e = getenv("HICCL_DEBUG");
+  return e && atoi(e) != 0;
+}
+
+static int check_counters(const Exe& ex) {
+  if (!ex.d_cnt) return 0;
+  constexpr size_t kPiece = 1024;
+  uint32_t buf[2 * kPiece];
+  const size_t n = 2 * size_t(ex.ntasks);
+  for (size_t i = 0; i < n; i += kPiece) {
+    const size_t k = std::min(kPiece, n - i);
+    HIP_TRY(hipMemcpy(buf, ex.d_cnt + i, k * 4, hipMemcpyDeviceToHost));
+    for (size_t j = 0; j < k; ++j)
+      if (buf[j])
+        return fail(HICCL_ERR_STATE, std::string("debug check: the ") +
+                                         (i + j < ex.ntasks ? "dependency" : "tile") + " counter of task " +
+                                         std::to_string((i + j) % ex.ntasks) + " is not zero after the run");
+  }
+  for (size_t i = 0; i < ex.ncomm; i += kPiece) {
+    const size_t k = std::min<size_t>(kPiece, ex.ncomm - i);
+    HIP_TRY(hipMemcpy(buf, ex.d_cnt + n + i, k * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(buf + kPiece, ex.d_comm_ntasks + i, k * 4, hipMemcpyDeviceToHost));
+    for (size_t j = 0; j < k; ++j)
+      if (buf[j] != buf[kPiece + j])
+        return fail(HICCL_ERR_STATE, "debug check: collective " + std::to_string(i + j) +
+                                         " has not got its task count back after the run");
+  }
+  uint32_t ctl[kCtlWords];
+  HIP_TRY(hipMemcpy(ctl, ex.d_cnt + n + ex.ncomm, sizeof(ctl), hipMemcpyDeviceToHost));
+  for (int q = 0; q < kMaxQueues; ++q)
+    if (ctl[q * kLine]) return fail(HICCL_ERR_STATE, "debug check: a claim counter is not zero after the run");
+  if (ctl[CTL_EXIT] || ctl[CTL_ABORT])
+    return fail(HICCL_ERR_STATE, "debug check: the exit or abort word is not zero after the run");
+  return 0;
+}
+
 static int read_status(const Exe& ex, int* status) {
   uint32_t st = 0;
   uint32_t* ctl = ex.d_cnt + 2 * size_t(ex.ntasks) + ex.ncomm;
@@ -1620,6 +1663,8 @@ static int read_status(const Exe& ex, int* status) {
     HIP_TRY(hipMemcpy(ctl + CTL_STATUS, &z, 4, hipMemcpyHostToDevice));
   }
   *status = int(st);
+  if (debug_checks())
+    if (int rc = check_counters(ex)) return rc;
   return 0;
 }
 

@@ -321,6 +321,48 @@ def test_spin_limit_abort_is_clean_and_recoverable(torch_cuda):
     c.close()
 
 
+@pytest.mark.parametrize("mode", ["persistent", "staged"])
+def test_debug_counter_check_after_runs(torch_cuda, mode, monkeypatch):
+    """HICCL_DEBUG=1 makes every wait read back the task table's counters: after normal runs, after runs
+    that gave up a dependency wait (TIMEOUT, counters still reset by the last workgroup) and after a batch
+    run, every counter is where the next run expects it, so no wait reports STATE, and results stay exact."""
+    torch = torch_cuda
+    from paper_2408_05962_amd import Batch
+    from paper_2408_05962_amd import collectives as CO
+    from paper_2408_05962_amd.hiccl import ERR_TIMEOUT, HicclError
+    monkeypatch.setenv("HICCL_DEBUG", "1")
+    name, p, h, d = "all_reduce", 16, [2, 4, 2], 4096
+    sends = _host_inputs(name, p, d, "int32", 78)
+    S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+    R = torch.zeros((p, H.recv_len(name, p, d)), dtype=torch.int32, device="cuda")
+    c = CO.make(name, p, "int32", [S[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=h, stripe=4,
+                pipeline=2, tile_bytes=1024, exec_mode=mode)
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        R.zero_()
+        c.run(st)
+        c.wait()
+        out = R.cpu().numpy()
+        H.check_result(name, {r: out[r] for r in range(p)}, sends, "int32")
+    if mode == "persistent":
+        c.set_spin_limit(1)
+        for _ in range(3):
+            c.run(st)
+            try:
+                c.wait()
+            except HicclError as e:
+                assert e.code == ERR_TIMEOUT
+        c.set_spin_limit(1 << 20)
+    R.zero_()
+    b = Batch([c], "persistent" if mode == "persistent" else "staged")
+    b.run(st)
+    b.wait()
+    out = R.cpu().numpy()
+    H.check_result(name, {r: out[r] for r in range(p)}, sends, "int32")
+    b.close()
+    c.close()
+
+
 @pytest.mark.parametrize("name,p,h", [("all_reduce", 1, [1]), ("broadcast", 1, [1]), ("all_reduce", 2, [1, 2]),
                                       ("all_reduce", 4, [4, 1]), ("all_to_all", 3, [3]), ("reduce_scatter", 6, [3, 1, 2])])
 @pytest.mark.parametrize("mode", ["persistent", "staged"])
