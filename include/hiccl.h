@@ -364,8 +364,8 @@ int hiccl_batch_wait(hiccl_batch_t batch);
 /* Completion times (ns, relative to the batch start) of each collective of
  * the last run. Persistent forms: the device clock at the moment its last
  * task retired. Graph / serial: the device clock when its last launch
- * finished. Staged: stream events, the end of its last stage launch. `ns`
- * has n entries. */
+ * finished. Staged: stream events, the end of its last stage launch. An
+ * empty collective (count 0: no task) reports 0. `ns` has n entries. */
 int hiccl_batch_times(hiccl_batch_t batch, uint64_t* ns, int n);
 int hiccl_batch_destroy(hiccl_batch_t batch);
 

@@ -2191,7 +2191,8 @@ int hiccl_batch_times(hiccl_batch_t b, uint64_t* ns, int n) {
     HIP_TRY(hipEventSynchronize(b->ev));
     for (int i = 0; i < n; ++i) {
       float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, b->stage_ev[0], b->stage_ev[size_t(b->last_stage[i]) + 1]));
+      if (!b->comms[i]->c.plan.tasks.empty())   // an empty collective has nothing to finish: 0
+        HIP_TRY(hipEventElapsedTime(&ms, b->stage_ev[0], b->stage_ev[size_t(b->last_stage[i]) + 1]));
       ns[i] = uint64_t(double(ms) * 1e6);
     }
     return HICCL_SUCCESS;
@@ -2203,15 +2204,17 @@ int hiccl_batch_times(hiccl_batch_t b, uint64_t* ns, int n) {
     start.push_back(t[n]);
   } else {
     for (int i = 0; i < n; ++i) {
+      if (b->each[i].ntiles == 0) continue;   // an empty collective launches nothing and reports 0
       unsigned long long t[2];
       HIP_TRY(hipMemcpy(t, b->each[i].d_times, sizeof(t), hipMemcpyDeviceToHost));
       stamp[i] = t[0];
       start.push_back(t[1]);
     }
   }
-  unsigned long long t0 = *std::min_element(start.begin(), start.end());
+  // stamps of 0 were never written (empty collectives; a merged table with no tile at all)
+  const unsigned long long t0 = start.empty() ? 0ull : *std::min_element(start.begin(), start.end());
   for (int i = 0; i < n; ++i)
-    ns[i] = stamp[i] >= t0 ? uint64_t(double(stamp[i] - t0) * 1e9 / b->clock_hz) : 0;
+    ns[i] = t0 && stamp[i] >= t0 ? uint64_t(double(stamp[i] - t0) * 1e9 / b->clock_hz) : 0;
   return HICCL_SUCCESS;
 }
 

@@ -90,6 +90,54 @@ def test_batch_matches_oracle_and_alone(torch_cuda, mode, group_mb, monkeypatch)
         it["comm"].close()
 
 
+@pytest.mark.parametrize("mode", ["persistent", "graph", "serial", "persistent_sjf", "staged"])
+def test_batch_with_empty_members(torch_cuda, mode):
+    """Empty collectives (count 0: no task) between real ones: every form runs, the real results equal the
+    oracle, the empty members report a completion time of 0 and the others a positive one below a second
+    (an empty member must not shift the others' time origin)."""
+    torch = torch_cuda
+    import synth
+    from paper_2408_05962_amd import Batch, Comm
+    from paper_2408_05962_amd import collectives as CO
+    p, h, d = 8, [2, 4], 8192
+    comms, real = [], []
+    for i in range(5):
+        if i % 2 == 0:
+            x = torch.zeros(p, device="cuda")
+            c = Comm(p, "float32")
+            c.add_multicast([x[r] for r in range(p)], [x[r] for r in range(p)], 0, 0, [1, 2, 3])
+            c.set_hierarchy(h)
+            c.init()
+            comms.append(c)
+            continue
+        sends = [np.asarray(x) for x in synth.rank_buffers("int32", 8, i, p, H.send_len("all_reduce", p, d))]
+        S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+        R = torch.zeros((p, H.recv_len("all_reduce", p, d)), dtype=S.dtype, device="cuda")
+        c = CO.make("all_reduce", p, "int32", [S[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=h)
+        comms.append(c)
+        real.append((i, S, R, sends))
+    b = Batch(comms, mode)
+    st = torch.cuda.current_stream()
+    for _ in range(2):
+        for _, _, R, _ in real:
+            R.zero_()
+        b.run(st)
+        b.wait()
+        torch.cuda.synchronize()
+        times = b.times_ns()
+        for i, t in enumerate(times):
+            if i % 2 == 0:
+                assert t == 0, (mode, times)
+            else:
+                assert 0 < t < 10**9, (mode, times)
+        for _, _, R, sends in real:
+            out = R.cpu().numpy()
+            H.check_result("all_reduce", {r: out[r] for r in range(p)}, sends, "int32", h=h)
+    b.close()
+    for c in comms:
+        c.close()
+
+
 @pytest.mark.parametrize("mode", ["persistent", "persistent_sjf", "staged"])
 def test_grouped_batch_completes_group_by_group(torch_cuda, mode, monkeypatch):
     """With groups of about 1 MiB of executed bytes, the merged forms finish their members in group order:
