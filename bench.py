@@ -819,6 +819,8 @@ def main():
     ap.add_argument("--batch", action="store_true", help="(default) measure the batching form: 512 collectives, "
                     "batched vs one launch per collective, throughput and p50/p99 latency")
     ap.add_argument("--no-batch", action="store_true", help="skip the batching form")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="measure only the batching form and print its JSON object (for a kernel trace of it)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving form (Poisson requests)")
     ap.add_argument("--serve-requests", type=int, default=500, help="requests per arrival rate")
     ap.add_argument("--serve-rates", default="0.5,0.9,1.2",
@@ -842,6 +844,9 @@ def main():
     from paper_2408_05962_amd import collectives as CO
 
     torch.cuda.init()
+    if args.only_batch:
+        print(json.dumps({"batching": batch_bench(torch)}), flush=True)
+        return
     dev = torch.device("cuda:0")
     st = torch.cuda.current_stream()
     S_el = S_BYTES // 4

@@ -141,17 +141,28 @@ def _digests():
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--trace", required=True)
+    ap.add_argument("--trace", help="kernel-trace run of the headline (with the four counter runs below)")
     ap.add_argument("--trace-log", help="captured output of the trace run (bench.py's JSON line)")
     for mode in ("staged", "persistent"):
-        ap.add_argument(f"--fetch-{mode}", required=True)
-        ap.add_argument(f"--write-{mode}", required=True)
+        ap.add_argument(f"--fetch-{mode}")
+        ap.add_argument(f"--write-{mode}")
     ap.add_argument("--precision-trace", help="kernel-trace run of the precision form (optional)")
     ap.add_argument("--precision-log", help="captured output of that run (bench.py's JSON line)")
+    ap.add_argument("--batch-trace", help="kernel-trace run of the batching form alone (optional)")
+    ap.add_argument("--batch-log", help="captured output of that run (bench.py --only-batch's JSON line)")
     ap.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     args = ap.parse_args()
     if args.precision_trace:
         _precision(args)
+    if args.batch_trace:
+        _batch(args)
+    if not args.trace:
+        print(f"wrote summaries to {args.out}")
+        return
+    missing = [f"--{k}-{m}" for k in ("fetch", "write") for m in ("staged", "persistent")
+               if not getattr(args, f"{k}_{m}")]
+    if missing:
+        raise SystemExit(f"--trace needs {' '.join(missing)}")
     P = plans()
     src, isa = _digests()
     line = _bench_line(args.trace_log)
@@ -216,6 +227,75 @@ Commands (from the repository root on one MI355X), then this summary:
 
 
 PRECISION_ARGS = "--steps 1 --warmup 0 --no-batch --no-alt --no-cpu-baseline --no-serve"
+BATCH_ARGS = "--only-batch"
+BATCH_FORMS = ("persistent", "persistent_sjf", "defaults_persistent")
+
+
+def _batch(args):
+    """Kernel stats of the batching form run alone, and the merged persistent launches in it.
+
+    The run times its forms in a fixed order (bench.py batch_bench: serial, graph, persistent,
+    persistent_sjf, staged, then serial and persistent with the defaults), each as one warm run and 3
+    timed runs. A merged persistent launch of the 512-collective batch is the only dispatch of
+    hiccl_persistent longer than 6 ms (the 256-collective tuning batch takes about 4 ms, a single member at
+    most about 0.5 ms), so those dispatches in order are the three merged persistent forms, 4 each."""
+    line = None
+    if args.batch_log and os.path.exists(args.batch_log):
+        for raw in open(args.batch_log):
+            raw = raw.strip()
+            if raw.startswith("{") and '"batching"' in raw:
+                line = json.loads(raw)["batching"]
+    disp = trace_dispatches(args.batch_trace, "hiccl_persistent<256, false>")
+    long_ms = [(e - s) / 1e6 for s, e in disp if (e - s) > 6e6]
+    rows = []
+    if len(long_ms) == 4 * len(BATCH_FORMS):
+        for i, form in enumerate(BATCH_FORMS):
+            timed = long_ms[4 * i + 1: 4 * i + 4]
+            ev = line[form]["makespan_ms"] if line and form in line else "—"
+            exec_b = (line or {}).get("sum_exec_bytes")
+            frac = f"{exec_b / (statistics.median(timed) * 1e6) / PEAK:.3f}" if exec_b else "—"
+            rows.append(f"| {form} | {', '.join(f'{t:.3f}' for t in timed)} | {statistics.median(timed):.3f} | "
+                        f"{ev} | {frac} |")
+    else:
+        rows.append(f"| (found {len(long_ms)} dispatches over 6 ms, expected {4 * len(BATCH_FORMS)}) | | | | |")
+    forms = ""
+    if line:
+        forms = "\n".join(f"| {k} | {line[k]['makespan_ms']} | {line[k]['hbm_frac']} | {line[k]['latency_us_p50']} | "
+                          f"{line[k]['latency_us_p99']} |"
+                          for k in ("serial", "graph", "persistent", "persistent_sjf", "staged",
+                                    "defaults_serial", "defaults_persistent") if k in line)
+    _, isa = _digests()
+    md = f"""# Batching form: 512 collectives over 8 ranks as {{2,4}}, 4 KiB-64 MiB per rank, float32 / int32
+
+Command (from the repository root on one MI355X), then this summary:
+
+    rocprofv3 --kernel-trace --stats --output-format csv -d {args.batch_trace} -o batch -- python3 bench.py {BATCH_ARGS}
+    python rocprof_summary.py --batch-trace {args.batch_trace} --batch-log <captured output>
+
+The merged persistent forms are one `hiccl_persistent<256, false>` dispatch per run (members in groups of about 1 GiB of executed bytes, claimed along group-stage diagonals). Executed bytes per run: {(line or {}).get('sum_exec_bytes', '—')}.
+
+## Kernel stats (rocprofv3 --stats)
+
+{_stats_table(args.batch_trace)}
+
+## Merged persistent launches in the trace (the 3 timed runs of each form, ms)
+
+| form | trace durations | median | bench.py makespan (HIP events) | executed fraction of 8 TB/s (trace) |
+|---|---|---|---|---|
+{chr(10).join(rows)}
+
+## The same run's bench.py batching results
+
+Under the kernel trace the captured graph replays much more slowly than without it; its figure here is the profiler's, not the form's.
+
+| form | makespan ms | executed fraction of 8 TB/s | latency p50 us | p99 us |
+|---|---|---|---|---|
+{forms}
+
+ kernel instructions sha256 (paper_2408_05962_amd/build.py): {isa}
+"""
+    with open(os.path.join(args.out, "hiccl_persistent_batch_512_collectives_8r.md"), "w") as f:
+        f.write(md)
 
 
 def _precision(args):

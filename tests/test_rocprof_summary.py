@@ -95,3 +95,40 @@ def test_summary_from_synthetic_csv(tmp_path, monkeypatch):
     per = (out / "hiccl_staged_per_stage_six_collectives_16r_64MiB.md").read_text()
     assert "| broadcast | 0 |" in per and f"| {RS.bench.SIX[-1]} |" in per
     assert "| 1.0 |" in per          # stage 0's median: 1000 ns
+
+
+def test_batch_summary_from_synthetic_csv(tmp_path, monkeypatch):
+    """The batching-form summary picks the dispatches of hiccl_persistent longer than 6 ms as the three
+    merged persistent forms, 4 each (one warm, 3 timed), and reports their median beside bench.py's
+    makespan and the executed fraction of peak."""
+    import sys
+    sys.path.insert(0, ROOT)
+    try:
+        import rocprof_summary as RS
+    except ImportError as e:
+        pytest.skip(str(e))
+    disp, t = [], 0
+    for _ in range(50):                                  # members and the tuning batch: all shorter than 6 ms
+        disp.append((PERSIST, t, t + 4_000_000))
+        t += 4_000_010
+    for base in (9_000_000, 9_100_000, 9_200_000):       # persistent, persistent_sjf, defaults_persistent
+        for k in range(4):
+            dur = base + (500_000 if k == 0 else 1000 * k)   # the warm run is slower and left out
+            disp.append((PERSIST, t, t + dur))
+            t += dur + 10
+    _trace(str(tmp_path / "batch"), disp)
+    line = {"batching": {"sum_exec_bytes": 72 * 10 ** 9,
+                         **{k: {"makespan_ms": 9.0, "hbm_frac": 0.8, "latency_us_p50": 1.0, "latency_us_p99": 2.0}
+                            for k in ("serial", "persistent", "persistent_sjf", "staged", "defaults_persistent")}}}
+    log = tmp_path / "batch.log"
+    log.write_text("[bench] progress\n" + json.dumps(line) + "\n")
+    out = tmp_path / "profiles"
+    out.mkdir()
+    monkeypatch.setattr(sys, "argv", ["rocprof_summary.py", "--batch-trace", str(tmp_path / "batch"),
+                                      "--batch-log", str(log), "--out", str(out)])
+    RS.main()
+    md = (out / "hiccl_persistent_batch_512_collectives_8r.md").read_text()
+    # persistent: timed runs 9.001, 9.002, 9.003 ms -> median 9.002 ms; 72 GB / 9.002 ms / 8 TB/s = 0.99978
+    assert "| persistent | 9.001, 9.002, 9.003 | 9.002 | 9.0 | 1.000 |" in md
+    assert "| defaults_persistent | 9.201, 9.202, 9.203 | 9.202 |" in md
+    assert "| staged | 9.0 | 0.8 | 1.0 | 2.0 |" in md
