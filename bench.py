@@ -318,6 +318,29 @@ def sweep_bench(torch):
         _progress(f"pipeline sweep m={m}: {row}")
     out["pipeline_depth_all_reduce"] = rows
 
+    # task timeline of the persistent executor (hiccl_set_trace): how much the dependency stages of one
+    # All-Reduce overlap in time at pipeline depth 1 and 8 (the picture of Sec. 4.5, from the device clock)
+    import numpy as np
+    tl = {}
+    for m in (1, 8):
+        c, snd, rcv = mk("all_reduce", HIER, STRIPE, m, "persistent")
+        c.set_trace(True)
+        for _ in range(3):
+            c.run(st)
+            c.wait()
+        start, end = c.trace()
+        stage = np.array([t["stage"] for t in c.plan_tasks()])
+        span = int(end.max())
+        windows = [[round(int(start[stage == k].min()) / 1e3, 1), round(int(end[stage == k].max()) / 1e3, 1)]
+                   for k in np.unique(stage)]
+        busy = sum(w[1] - w[0] for w in windows)
+        tl[f"m{m}"] = {"span_us": round(span / 1e3, 1), "stage_windows_us": windows,
+                       "stage_busy_over_span": round(busy / (span / 1e3), 3), "tasks": len(start)}
+        c.close()
+        del snd, rcv
+        _progress(f"timeline m={m}: {tl[f'm{m}']}")
+    out["task_timeline_all_reduce_persistent"] = tl
+
     # ring(4) + tree vs tree on 16 ranks as {4,4} (Sec. 4.4)
     ring = {}
     for name in SIX:

@@ -269,6 +269,22 @@ int hiccl_set_claim(hiccl_comm_t comm, int queues, int batch);
  * every workgroup exits and hiccl_wait returns TIMEOUT. */
 int hiccl_set_spin_limit(hiccl_comm_t comm, uint32_t polls);
 
+/* Task timeline of the persistent executor (the pipelining picture of
+ * Sec. 4.5: which transfers of which channel overlap in time). With trace on
+ * (1), runs of this communicator on the persistent executor stamp, for every
+ * task, the device clock when its first tile starts and when its last tile
+ * retires; off (0, the default) they stamp nothing. Changing it drops the
+ * uploaded tables (the next run uploads them again). INVALID_ARG for other
+ * values. */
+int hiccl_set_trace(hiccl_comm_t comm, int on);
+/* The last traced run's timeline, after hiccl_wait: start_ns[i] / end_ns[i]
+ * for plan task i (the order of hiccl_plan_tasks), in ns from the earliest
+ * task start of that run. Arrays of ntasks entries, ntasks = the plan's task
+ * count (INVALID_ARG otherwise). STATE if trace is off, the executor is not
+ * the persistent one, or the communicator has no traced run of its own (a
+ * batch or hiccl_run_static run is not traced). */
+int hiccl_trace_tasks(hiccl_comm_t comm, uint64_t* start_ns, uint64_t* end_ns, size_t ntasks);
+
 /* ------------------------------------------------------------- accounting */
 
 /* Communication volume of the plan, per hierarchy level: the per-level
@@ -318,6 +334,12 @@ int hiccl_plan_info(hiccl_comm_t comm, hiccl_plan_info_t* info);
 
 /* Copy up to `cap` task descriptions, in claim order, into `out`. */
 int hiccl_plan_tasks(hiccl_comm_t comm, hiccl_task_info_t* out, size_t cap, size_t* n);
+/* The dependency edges of the plan (Sec. 3.3 fences, Sec. 4.5 channels):
+ * edge e says task to[e] may start only after task from[e] has finished
+ * (indices in the order of hiccl_plan_tasks). Copies up to `cap` edges;
+ * *n = the total. INVALID_ARG for NULL outputs with cap > 0, STATE before
+ * hiccl_init. */
+int hiccl_plan_edges(hiccl_comm_t comm, uint32_t* from, uint32_t* to, size_t cap, size_t* n);
 
 /* Schedule checker (debugging aid; never used by hiccl_run): executes the
  * plan on HOST memory — the registered buffers must be host pointers — in

@@ -69,6 +69,9 @@ struct ExecArgs {
   uint32_t ntiles, ntasks, ncomm, spin_limit;
   uint32_t queues;            // tile queues (tile t belongs to queue t % queues)
   uint32_t batch;             // tiles claimed per atomic
+  unsigned long long* trace;  // trace on: [ntasks] clocks when each task's first tile started, then
+                              // [ntasks] clocks when its last tile retired; else null
+  uint32_t pad_[2];
 };
 
 #define HIP_TRY(expr)                                                                       \
@@ -667,12 +670,14 @@ struct TileRef {
 // traffic at all. The tile's data stores are device-coherent and complete
 // (every worker wave that ran it waited before the workgroup barrier that
 // precedes this call), so counting it is the release.
+template <bool TRACE = false>
 __device__ __forceinline__ void retire(const ExecArgs& a, const TileRef& r, uint32_t n = 1) {
-  if (!r.nsucc && !a.times) return;
+  if (!r.nsucc && !a.times && !TRACE) return;
   if (r.ntiles > 1) {
     uint32_t old = __hip_atomic_fetch_add(&a.done[r.k], n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old + n != r.ntiles) return;
   }
+  if (TRACE) a.trace[a.ntasks + r.k] = dev_clock();   // before the successors are released
   const uint32_t b = r.succ_begin, e = b + r.nsucc;
   for (uint32_t s = b; s < e; ++s)
     __hip_atomic_fetch_add(&a.pending[a.succ[s]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -770,8 +775,10 @@ __device__ __forceinline__ TileRef ref_of(const DevTask& t, uint32_t k) {
   return TileRef{k, t.nsucc, t.succ_begin, t.ntiles, t.comm};
 }
 
-template <int BLOCK, bool NARROW>
-__global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
+// TRACE: the body of hiccl_persistent_traced, used while a communicator's trace is on (a.trace set): it
+// stamps each task's start and end clocks; hiccl_persistent carries no trace code.
+template <int BLOCK, bool NARROW, bool TRACE>
+__device__ __forceinline__ void persistent_body(const ExecArgs& a) {
   __shared__ DevTask s_task[2];
   __shared__ uint32_t s_slot[2], s_q[2], s_flag;      // s_q: the posted tile's number within its task
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x) / 64;   // wave-uniform
@@ -809,6 +816,7 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
     const uint32_t tl = v & ~kNotReady;
     if (sched) {
       DevTask* next = &s_task[cur ^ 1];
+      if (TRACE && ready && lead && s_q[cur] == 0) a.trace[cur_ref.k] = dev_clock();   // the workers start it now
       if (ready) {
         // the workers run tl now: claim the next tile; it may depend on tl, so do not block on it
         uint32_t nx_l = kNoTile;
@@ -822,7 +830,7 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
           if (cur_ref.k == prev_ref.k) {
             ++held;
           } else {
-            retire(a, prev_ref, held + 1);
+            retire<TRACE>(a, prev_ref, held + 1);
             held = 0;
           }
         }
@@ -849,7 +857,7 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
         // the workers idle this iteration; everything of ours has retired once
         // tile i-1 has, so wait in full, then post tl again in the other slot
         if (lead && have_prev) {
-          retire(a, prev_ref, held + 1);
+          retire<TRACE>(a, prev_ref, held + 1);
           held = 0;
         }
         stage_desc(next, &s_task[cur], lane);
@@ -874,7 +882,7 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
     __syncthreads();
   }
   if (sched) {
-    if (lead && have_prev) retire(a, prev_ref, held + 1);
+    if (lead && have_prev) retire<TRACE>(a, prev_ref, held + 1);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -895,6 +903,15 @@ __global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
       a.ctl[CTL_EXIT] = 0;
     }
   }
+}
+
+template <int BLOCK, bool NARROW>
+__global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent(ExecArgs a) {
+  persistent_body<BLOCK, NARROW, false>(a);
+}
+template <int BLOCK, bool NARROW>
+__global__ __launch_bounds__(BLOCK + 64) void hiccl_persistent_traced(ExecArgs a) {
+  persistent_body<BLOCK, NARROW, true>(a);
 }
 
 // Device-clock stamp for stage launches (one thread): launched on the stream
@@ -1135,6 +1152,8 @@ struct Exe {
   uint32_t* d_cnt = nullptr;           // pending | done | comm_left | ctl
   uint32_t* d_comm_ntasks = nullptr;
   unsigned long long* d_times = nullptr;
+  unsigned long long* d_trace = nullptr;   // per-task start | end clocks (persistent, trace on)
+  std::vector<uint32_t> task_pos;          // one plan: table position of each plan task
   uint32_t ntasks = 0, ntiles = 0, ncomm = 0;
   std::vector<uint32_t> stage_tile_begin;
   int mode = HICCL_EXEC_PERSISTENT;
@@ -1165,6 +1184,8 @@ struct Exe {
     a.spin_limit = spin_limit;
     a.queues = queues;
     a.batch = batch;
+    a.trace = d_trace;
+    a.pad_[0] = a.pad_[1] = 0;
     return a;
   }
   void free_all() {
@@ -1180,6 +1201,7 @@ struct Exe {
       (void)hipFree(d_cnt);
       (void)hipFree(d_comm_ntasks);
       (void)hipFree(d_times);
+      (void)hipFree(d_trace);
       (void)hipSetDevice(cur);
     }
     *this = Exe();
@@ -1426,6 +1448,7 @@ static int build_image(const std::vector<const Plan*>& plans, const std::vector<
   std::vector<std::vector<uint32_t>> newidx(plans.size());
   for (uint32_t p = 0; p < plans.size(); ++p) newidx[p].resize(plans[p]->tasks.size());
   for (uint32_t i = 0; i < refs.size(); ++i) newidx[refs[i].plan][refs[i].idx] = i;
+  if (plans.size() == 1) ex.task_pos = newidx[0];
 
   size_t nt = refs.size();
   std::vector<DevTask>& h = img.tasks;
@@ -1595,8 +1618,12 @@ static int launch(const Exe& ex, hipStream_t st) {
   if (ex.ntiles == 0) return 0;
   ExecArgs a = ex.args();
   if (ex.mode == HICCL_EXEC_PERSISTENT) {
-    if (ex.narrow)
+    if (ex.narrow && a.trace)
+      hipLaunchKernelGGL((hiccl_persistent_traced<kNarrowBlock, true>), dim3(ex.grid), dim3(kNarrowBlock + 64), 0, st, a);
+    else if (ex.narrow)
       hipLaunchKernelGGL((hiccl_persistent<kNarrowBlock, true>), dim3(ex.grid), dim3(kNarrowBlock + 64), 0, st, a);
+    else if (a.trace)
+      hipLaunchKernelGGL((hiccl_persistent_traced<kBlock, false>), dim3(ex.grid), dim3(kBlock + 64), 0, st, a);
     else
       hipLaunchKernelGGL((hiccl_persistent<kBlock, false>), dim3(ex.grid), dim3(kBlock + 64), 0, st, a);
   } else {
@@ -1692,6 +1719,12 @@ static int ensure_device(Comm& c) {
   }
   int rc = upload({&c.plan}, {ws}, c.exec.mode, c.exec.grid, c.exec.spin_limit, false, s->exe, c.exec.queues,
                   c.exec.batch, 0, true);
+  if (!rc && c.exec.trace && c.exec.mode == HICCL_EXEC_PERSISTENT && s->exe.ntasks) {
+    const size_t bytes = 2 * size_t(s->exe.ntasks) * sizeof(unsigned long long);
+    if (hipMalloc(reinterpret_cast<void**>(&s->exe.d_trace), bytes) != hipSuccess ||
+        hipMemset(s->exe.d_trace, 0, bytes) != hipSuccess)
+      rc = fail(HICCL_ERR_HIP, "trace buffer");
+  }
   if (!rc && hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) != hipSuccess)
     rc = fail(HICCL_ERR_HIP, "event creation failed");
   if (rc) {
@@ -1775,6 +1808,36 @@ int hiccl_wait(hiccl_comm_t comm) {
   int status = 0;
   if (int rc = read_status(c.dev->exe, &status)) return rc;
   if (status) return fail(HICCL_ERR_TIMEOUT, "executor gave up a dependency wait (spin limit reached)");
+  return HICCL_SUCCESS;
+}
+
+int hiccl_trace_tasks(hiccl_comm_t comm, uint64_t* start_ns, uint64_t* end_ns, size_t ntasks) {
+  if (!comm || !start_ns || !end_ns) return fail(HICCL_ERR_INVALID_ARG, "NULL argument");
+  Comm& c = comm->c;
+  if (!c.planned) return fail(HICCL_ERR_STATE, "call hiccl_init first");
+  if (ntasks != c.plan.tasks.size()) return fail(HICCL_ERR_INVALID_ARG, "ntasks must be the plan's task count");
+  if (!c.exec.trace || c.exec.mode != HICCL_EXEC_PERSISTENT)
+    return fail(HICCL_ERR_STATE, "trace is off, or the executor is not the persistent one");
+  if (!ntasks) return HICCL_SUCCESS;
+  if (!c.dev || !c.dev->launched || c.last_static || c.dev->batch || !c.dev->exe.d_trace)
+    return fail(HICCL_ERR_STATE, "no traced run of this communicator (hiccl_run, then hiccl_wait)");
+  HIP_TRY(hipEventSynchronize(c.dev->ev));
+  const Exe& ex = c.dev->exe;
+  std::vector<unsigned long long> t(2 * size_t(ex.ntasks));
+  HIP_TRY(hipMemcpy(t.data(), ex.d_trace, t.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+  int khz = 0;
+  HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ex.device));
+  if (khz <= 0) return fail(HICCL_ERR_HIP, "device clock rate unknown");
+  unsigned long long t0 = ~0ull;
+  for (size_t i = 0; i < ex.ntasks; ++i)
+    if (t[i]) t0 = std::min(t0, t[i]);
+  const double ns_per_tick = 1e6 / double(khz);
+  for (size_t i = 0; i < ntasks; ++i) {
+    const uint32_t k = ex.task_pos[i];
+    const unsigned long long a = t[k], b = t[ex.ntasks + k];
+    start_ns[i] = a && a >= t0 ? uint64_t(double(a - t0) * ns_per_tick) : 0;
+    end_ns[i] = b && b >= t0 ? uint64_t(double(b - t0) * ns_per_tick) : 0;
+  }
   return HICCL_SUCCESS;
 }
 

@@ -114,6 +114,7 @@ struct ExecCfg {
   uint32_t spin_limit = 1u << 22;
   int queues = 8;
   int batch = 4;
+  bool trace = false;            // persistent executor: stamp each task's start and end (hiccl_set_trace)
 };
 
 struct DeviceState;              // device.hip

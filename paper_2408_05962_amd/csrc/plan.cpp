@@ -1293,6 +1293,19 @@ int hiccl_set_claim(hiccl_comm_t comm, int queues, int batch) {
   return HICCL_SUCCESS;
 }
 
+int hiccl_set_trace(hiccl_comm_t comm, int on) {
+  CHECK_COMM(comm);
+  if (on != 0 && on != 1) return fail(HICCL_ERR_INVALID_ARG, "trace must be 0 or 1");
+  if (comm->c.exec.trace == (on != 0)) return HICCL_SUCCESS;
+  comm->c.exec.trace = on != 0;
+  if (comm->c.dev) {             // the next run uploads the tables with (or without) the trace buffer
+    device_state_free(comm->c.dev);
+    comm->c.dev = nullptr;
+  }
+  drop_static(comm->c);
+  return HICCL_SUCCESS;
+}
+
 int hiccl_set_spin_limit(hiccl_comm_t comm, uint32_t polls) {
   CHECK_COMM(comm);
   if (polls == 0) return fail(HICCL_ERR_INVALID_ARG, "spin limit must be >= 1");
@@ -1410,6 +1423,25 @@ int hiccl_plan_tasks(hiccl_comm_t comm, hiccl_task_info_t* out, size_t cap, size
     o.offset = t.offset;
   }
   if (n) *n = c.plan.tasks.size();
+  return HICCL_SUCCESS;
+}
+
+int hiccl_plan_edges(hiccl_comm_t comm, uint32_t* from, uint32_t* to, size_t cap, size_t* n) {
+  CHECK_COMM(comm);
+  const Comm& c = comm->c;
+  if (!c.planned) return fail(HICCL_ERR_STATE, "call hiccl_init first");
+  size_t total = 0;
+  for (const Task& t : c.plan.tasks) total += t.preds.size();
+  if (std::min(cap, total) && (!from || !to)) return fail(HICCL_ERR_INVALID_ARG, "NULL output");
+  size_t m = 0;
+  for (size_t i = 0; i < c.plan.tasks.size() && m < cap; ++i)
+    for (int p : c.plan.tasks[i].preds) {
+      if (m == cap) break;
+      from[m] = uint32_t(p);
+      to[m] = uint32_t(i);
+      ++m;
+    }
+  if (n) *n = total;
   return HICCL_SUCCESS;
 }
 

@@ -78,6 +78,8 @@ def lib():
             "hiccl_set_share": [vp, i],
             "hiccl_set_exec": [vp, i, sz, i, i],
             "hiccl_set_spin_limit": [vp, C.c_uint32],
+            "hiccl_set_trace": [vp, i],
+            "hiccl_trace_tasks": [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.c_size_t],
             "hiccl_set_claim": [vp, i, i],
             "hiccl_set_grid": [vp, i],
             "hiccl_init": [vp],
@@ -89,6 +91,7 @@ def lib():
             "hiccl_query_bytes": [vp, pi, i, C.POINTER(u64), C.POINTER(u64), C.POINTER(u64)],
             "hiccl_plan_info": [vp, C.POINTER(PlanInfo)],
             "hiccl_plan_tasks": [vp, C.POINTER(TaskInfo), sz, C.POINTER(sz)],
+            "hiccl_plan_edges": [vp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), sz, C.POINTER(sz)],
             "hiccl_validate_host": [vp, u64, i],
             "hiccl_batch_create": [C.POINTER(vp), i, i, C.POINTER(vp)],
             "hiccl_batch_run": [vp, vp],
@@ -233,6 +236,19 @@ class Comm:
     def set_spin_limit(self, polls):
         return check(lib().hiccl_set_spin_limit(self.h, int(polls)))
 
+    def set_trace(self, on=True):
+        return check(lib().hiccl_set_trace(self.h, 1 if on else 0))
+
+    def trace(self):
+        """(start_ns, end_ns) of every plan task in the last traced run (numpy uint64 arrays)."""
+        import numpy as np
+        n = self.plan_info()["ntasks"]
+        start = np.zeros(max(1, n), np.uint64)
+        end = np.zeros(max(1, n), np.uint64)
+        p = C.POINTER(C.c_uint64)
+        check(lib().hiccl_trace_tasks(self.h, start.ctypes.data_as(p), end.ctypes.data_as(p), n))
+        return start[:n], end[:n]
+
     def init(self):
         return check(lib().hiccl_init(self.h))
 
@@ -286,6 +302,17 @@ class Comm:
             d["src_rank"] = list(t.src_rank[:min(t.nsrc, MAX_SRC)])
             out.append(d)
         return out
+
+    def plan_edges(self):
+        """Dependency edges (from, to) of the plan, as two numpy uint32 arrays of task indices."""
+        import numpy as np
+        n = C.c_size_t()
+        check(lib().hiccl_plan_edges(self.h, None, None, 0, C.byref(n)))
+        a = np.zeros(max(1, n.value), np.uint32)
+        b = np.zeros(max(1, n.value), np.uint32)
+        p = C.POINTER(C.c_uint32)
+        check(lib().hiccl_plan_edges(self.h, a.ctypes.data_as(p), b.ctypes.data_as(p), n.value, C.byref(n)))
+        return a[:n.value], b[:n.value]
 
     def validate_host(self, seed=0, norders=3):
         return check(lib().hiccl_validate_host(self.h, int(seed), int(norders)))

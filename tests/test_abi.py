@@ -475,3 +475,57 @@ def test_autotune_batch_argument_errors(hc):
     assert lib.hiccl_autotune_batch(None, 0, one, 1, one, 1, one, 1, tiles, 1, 0, 1, 1, None, out_i, out_p, out_t,
                                     C.byref(ms)) == hc.ERR_INVALID_ARG
     c.close()
+
+
+def test_trace_argument_and_state_errors(hc):
+    """hiccl_set_trace takes 0 or 1; hiccl_trace_tasks wants the plan's task count and a traced persistent
+    run of the communicator itself, and says STATE (before any device call) when there is none."""
+    import ctypes as C
+    lib = hc.lib()
+    assert lib.hiccl_set_trace(None, 1) == hc.ERR_INVALID_ARG
+    c = hc.Comm(4, "float32")
+    s, r = _bufs(4, 64), _bufs(4, 64)
+    from paper_2408_05962_amd import collectives as CO
+    CO.compose(c, "all_reduce", s, r, 16)
+    c.set_hierarchy([2, 2])
+    assert lib.hiccl_set_trace(c.h, 2) == hc.ERR_INVALID_ARG
+    buf = (C.c_uint64 * 64)()
+    assert lib.hiccl_trace_tasks(c.h, buf, buf, 0) == hc.ERR_STATE              # not initialized
+    c.init()
+    nt = c.plan_info()["ntasks"]
+    assert lib.hiccl_trace_tasks(c.h, buf, buf, nt) == hc.ERR_STATE             # trace off
+    c.set_trace(True)
+    assert lib.hiccl_trace_tasks(c.h, buf, buf, nt + 1) == hc.ERR_INVALID_ARG   # wrong count
+    assert lib.hiccl_trace_tasks(c.h, None, buf, nt) == hc.ERR_INVALID_ARG
+    assert lib.hiccl_trace_tasks(c.h, buf, buf, nt) == hc.ERR_STATE             # no run yet
+    c.set_exec("staged", 0, 0, "stage")                                        # discards the plan
+    c.init()
+    assert lib.hiccl_trace_tasks(c.h, buf, buf, c.plan_info()["ntasks"]) == hc.ERR_STATE   # staged executor
+    c.close()
+
+
+def test_plan_edges_match_the_plan(hc):
+    """hiccl_plan_edges: as many edges as hiccl_plan_info counts, each task's in-degree equals its npred,
+    every edge runs from a lower stage to a higher one, and inside one primitive's tree the edges stay
+    within a channel (Sec. 4.5: channel c of a node depends on channel c of its predecessors)."""
+    import numpy as np
+    from paper_2408_05962_amd import collectives as CO
+    p, d = 16, 4096
+    s, r = _bufs(p, d * p), _bufs(p, d * p)
+    c = hc.Comm(p, "float32")
+    CO.compose(c, "all_reduce", s, r, d)
+    c.set_hierarchy([2, 4, 2])
+    c.set_stripe(4)
+    c.set_pipeline(4)
+    c.init()
+    info = c.plan_info()
+    tasks = c.plan_tasks()
+    a, b = c.plan_edges()
+    assert len(a) == info["nedges"] > 0
+    indeg = np.bincount(b, minlength=len(tasks))
+    assert [int(x) for x in indeg] == [t["npred"] for t in tasks]
+    for x, y in zip(a.tolist(), b.tolist()):
+        assert tasks[x]["stage"] < tasks[y]["stage"]
+        if tasks[x]["prim"] == tasks[y]["prim"]:
+            assert tasks[x]["channel"] == tasks[y]["channel"]
+    c.close()
