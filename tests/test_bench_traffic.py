@@ -47,3 +47,15 @@ def test_built_digest_against_the_profiles():
     assert (bench.measured_traffic("staged", 0, 0) is not None) == same
     if not same:
         pytest.skip("kernels changed since the committed counters were taken: traffic is reported as null")
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N with N above 1 prints one JSON line saying that this benchmark runs on one GPU and
+    exits with status 2, before it touches a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in line["error"]
