@@ -282,7 +282,9 @@ int hiccl_set_trace(hiccl_comm_t comm, int on);
  * task start of that run. Arrays of ntasks entries, ntasks = the plan's task
  * count (INVALID_ARG otherwise). STATE if trace is off, the executor is not
  * the persistent one, or the communicator has no traced run of its own (a
- * batch or hiccl_run_static run is not traced). */
+ * batch or hiccl_run_static run is not traced). After a run that gave up a
+ * dependency wait (TIMEOUT) the tasks it did not reach keep the stamps of an
+ * earlier run. */
 int hiccl_trace_tasks(hiccl_comm_t comm, uint64_t* start_ns, uint64_t* end_ns, size_t ntasks);
 
 /* ------------------------------------------------------------- accounting */
