@@ -1317,8 +1317,6 @@ struct Image {
   std::vector<std::pair<size_t, size_t>> extra_fix;
 };
 
-// Build the host image of the merged table of `plans` and fill the host-side
-// fields of `ex` (stage boundaries, launch shape); no device pointer is set.
 // Executed bytes per group of a merged batch (see build_image): 1 GiB for the persistent launch, 4 GiB
 // for stage launches, which pay a launch per group and stage (both measured best on the 512-collective
 // batch). HICCL_BATCH_GROUP_MB overrides it (MiB; 0 = one group).
@@ -1330,6 +1328,8 @@ static uint64_t batch_group_bytes(int mode) {
   return uint64_t(mode == HICCL_EXEC_PERSISTENT ? 1 : 4) << 30;
 }
 
+// Build the host image of the merged table of `plans` and fill the host-side
+// fields of `ex` (stage boundaries, launch shape); no device pointer is set.
 // Flatten plans into one device task table. ws_base[i] is plan i's workspace.
 // merge: 0 = members in batch order; 1 = smallest collective first (by
 // executed bytes). Several members run in groups (see below).
