@@ -98,3 +98,29 @@ def test_trace_overlaps_channels(torch_cuda):
         c.close()
     assert sums[8] > 1.0, sums
     assert sums[8] > sums[1], sums
+
+
+@pytest.mark.parametrize("name", H.SIX)
+def test_trace_dependencies_every_collective(torch_cuda, name):
+    """Every one of the six collectives at 16 ranks as {2,4,2}, s = 4, m = 4 (the persistent executor's
+    claim orders differ: stage order for the copy-only collectives, diagonal channel groups for the
+    reduction ones): no successor starts before its predecessor finished, and the result equals the
+    oracle."""
+    torch = torch_cuda
+    import synth
+    from paper_2408_05962_amd import collectives as CO
+    p, h, s, m, d = 16, [2, 4, 2], 4, 4, 16384
+    sends = [np.asarray(x) for x in synth.rank_buffers("int32", 10, H.SIX.index(name), p, H.send_len(name, p, d))]
+    S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+    R = torch.zeros((p, H.recv_len(name, p, d)), dtype=S.dtype, device="cuda")
+    c = CO.make(name, p, "int32", [S[r] for r in range(p)], [R[r] for r in range(p)], d, hierarchy=h, stripe=s,
+                pipeline=m)
+    c.set_trace(True)
+    st = torch.cuda.current_stream()
+    c.run(st)
+    c.wait()
+    _check_timeline(c)
+    out = R.cpu().numpy()
+    ranks = [0] if name == "reduce" else range(p)
+    H.check_result(name, {r: out[r] for r in ranks}, sends, "int32", h=h, s=s)
+    c.close()
