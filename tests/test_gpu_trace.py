@@ -124,3 +124,37 @@ def test_trace_dependencies_every_collective(torch_cuda, name):
     ranks = [0] if name == "reduce" else range(p)
     H.check_result(name, {r: out[r] for r in ranks}, sends, "int32", h=h, s=s)
     c.close()
+
+
+@pytest.mark.parametrize("name", ["broadcast", "reduce", "all_gather", "reduce_scatter", "all_reduce_bcast"])
+def test_trace_two_step_fences(torch_cuda, name):
+    """The two-step rows of Table 2: a fence between the steps makes a task of the second step wait only
+    for the first-step tasks whose ranges overlap its own (Sec. 3.3). On the device clock, every such
+    edge is respected, and the result equals the direct definition."""
+    torch = torch_cuda
+    import synth
+    from paper_2408_05962_amd import Comm
+    from paper_2408_05962_amd import collectives as CO
+    p, h, s, m, d = 16, [2, 4, 2], 4, 2, 4096 + 3
+    base = "all_reduce" if name == "all_reduce_bcast" else name
+    sends = [np.asarray(x) for x in synth.rank_buffers("int32", 11, len(name), p, H.send_len(base, p, d))]
+    S = torch.stack([torch.from_numpy(x) for x in sends]).to("cuda")
+    R = torch.full((p, H.recv_len(base, p, d)), -7, dtype=torch.int32, device="cuda")
+    X = torch.zeros((p, d * p), dtype=torch.int32, device="cuda")
+    c = Comm(p, "int32")
+    CO.compose_multi(c, name, [S[r] for r in range(p)], [R[r] for r in range(p)], [X[r] for r in range(p)], d,
+                     root=p - 1)
+    c.set_hierarchy(h)
+    c.set_stripe(s)
+    c.set_pipeline(m)
+    c.set_trace(True)
+    c.init()
+    c.run(torch.cuda.current_stream())
+    c.wait()
+    _check_timeline(c)
+    steps = {t["step"] for t in c.plan_tasks()}
+    assert len(steps) == 2
+    out = R.cpu().numpy()
+    ranks = [p - 1] if base in ("reduce", "gather") else range(p)
+    H.check_result(base, {r: out[r] for r in ranks}, sends, "int32", root=p - 1)
+    c.close()
